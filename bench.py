@@ -1,0 +1,239 @@
+#!/usr/bin/env python3
+"""Benchmark of the DVR hot path on one MI355X.
+
+One step = the feature pass of the 181x217x181 FP32 head phantom (gradient, 3-scale Hessian,
+curvature, vesselness) followed by the raymarch of all 360 perspective orbit views at 1024^2
+(8-knot TF, early termination at alpha >= 0.99).  Inputs are resident in HBM before the timed
+region; K steps are timed with HIP events on the stream the kernels are launched on.
+
+The JSON line's value is evaluated ray samples per second over the whole step (feature pass
+included).  Components: feature-pass voxels/s, raymarch samples/s, and forward+backward ms per
+view of the differentiable-render workload (128^3 phantom, 8 views at 512^2, L2 loss against a
+target from a perturbed 16-knot TF).  The roofline object covers the dominant kernel (the
+raymarch); the CPU baseline is the FP64 oracle on a bounded sample of the same step.
+"""
+from __future__ import annotations
+
+import argparse
+import hashlib
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "voxels/s (features), ray-samples/s + fwd+bwd ms/view; % HBM roofline"
+# Dense FP32 vector peak without packed-FP32 instructions (this build forbids them):
+# 256 CU x 4 SIMD x 16 lanes x 2 flop (FMA) x 2.4 GHz.
+PEAK_FP32_TFLOPS = 78.6432
+PEAK_FP32_PUBLISHED = 157.3
+PEAK_HBM_GBS = 8000.0
+# Algorithmic flops per raymarch sample (FMA = 2); see the design notes for the breakdown.
+FLOP_SHADED = 144
+FLOP_TRANSPARENT = 40
+RENDER_SOURCES = ["render.hip", "render_args.hpp", "common.hpp"]
+
+
+def log(msg):
+    print(f"[bench] {msg}", file=sys.stderr, flush=True)
+
+
+def source_sha(files):
+    h = hashlib.sha256()
+    for f in files:
+        with open(os.path.join(ROOT, "paper_2605_19737_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def load_traffic(kernel_key, sha):
+    path = os.path.join(ROOT, "profiles", "traffic.json")
+    if not os.path.exists(path):
+        return None
+    with open(path) as fh:
+        rec = json.load(fh).get(kernel_key)
+    if not rec or rec.get("source_sha") != sha:
+        return None
+    return rec
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--views", type=int, default=360, help="views per step (the workload has 360)")
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-backward-leg", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
+    args = ap.parse_args()
+    world = int(os.environ.get("WORLD_SIZE", "1"))
+    if args.gpus != 1 or world != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (the design notes describe how "
+              "the work would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2605_19737_amd as dvr
+    import phantoms
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    dvr.lib()
+
+    # ------------------------------------------------------------------ workload (inputs into HBM)
+    log("building the head phantom and cameras")
+    w = phantoms.c2(1024, 1024, nviews=args.views)
+    vol = torch.from_numpy(w.vol).to(dev)
+    knots = torch.from_numpy(w.tf_knots).to(dev)
+    tf = torch.from_numpy(w.tf_rgba).to(dev)
+    cams = [dvr.camera_struct(c) for c in w.cams]
+    nvox = vol.numel()
+    nz, ny, nx = vol.shape
+    feats = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float32)
+    wsb = dvr.features_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c)
+    ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    V = len(cams)
+    img = torch.empty((V, 1024, 1024, 4), dtype=torch.float32, device=dev)
+    counters = torch.zeros(2, dtype=torch.int64, device=dev)
+    stream = torch.cuda.current_stream()
+
+    def step(timing=None):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        dvr.features(vol, w.spacing, w.sigmas, c=w.c, out=feats, ws=ws)
+        e1.record(stream)
+        _, T, k = dvr.render(vol, feats, knots, tf, w.params, cams, out=img, counters=counters)
+        e2.record(stream)
+        if timing is not None:
+            timing.append((e0, e1, e2))
+        return T, k
+
+    log(f"warmup x{args.warmup}")
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    log(f"timing {args.steps} steps of {V} views")
+    timing = []
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(timing)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    t_feat = sum(a.elapsed_time(b) for a, b, _ in timing) / 1e3
+    t_rend = sum(b.elapsed_time(c) for _, b, c in timing) / 1e3
+    t_step = sum(a.elapsed_time(c) for a, _, c in timing) / 1e3
+    evaluated, shaded = (int(x) for x in counters.cpu().tolist())
+    log(f"step {1e3 * t_step / args.steps:.2f} ms (features {1e3 * t_feat / args.steps:.3f} ms, render "
+        f"{1e3 * t_rend / args.steps:.2f} ms); samples/step evaluated {evaluated:.4g} shaded {shaded:.4g}; wall {wall:.2f}s")
+
+    K = args.steps
+    samples_per_s = evaluated * K / t_step
+    render_sps = evaluated * K / t_rend
+    vox_per_s = nvox * K / t_feat
+    launches_per_step = math.ceil(V / 32)
+    render_launch_s = t_rend / (K * launches_per_step)
+    flops_per_step = shaded * FLOP_SHADED + (evaluated - shaded) * FLOP_TRANSPARENT
+    achieved_tflops = flops_per_step * K / t_rend / 1e12
+    sha = source_sha(RENDER_SOURCES)
+    tr = load_traffic("render_head_1024_persp", sha)
+    traffic = None
+    if tr is not None:
+        traffic = {"fetch_bytes_per_launch": tr["fetch_bytes_per_launch"],
+                   "write_bytes_per_launch": tr["write_bytes_per_launch"],
+                   "hbm_gbs": (tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]) / render_launch_s / 1e9,
+                   "views_per_launch": tr.get("views_per_launch"), "source_sha": sha}
+    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
+                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+                "traffic": traffic, "kernel": "k_render (FP32 planar, K<=8)",
+                "avg_launch_ms": round(1e3 * render_launch_s, 4),
+                "flops_per_launch": flops_per_step / launches_per_step,
+                "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4)}
+
+    comps = {"features_voxels_per_s": vox_per_s, "features_ms": 1e3 * t_feat / K,
+             "render_samples_per_s": render_sps, "render_ms_per_view": 1e3 * t_rend / (K * V),
+             "samples_evaluated_per_step": evaluated, "samples_shaded_per_step": shaded,
+             "rays_per_step": V * 1024 * 1024}
+
+    # ------------------------------------------------------------------ fwd+bwd ms/view leg
+    if not args.no_backward_leg:
+        log("differentiable-render leg: 128^3, 8 views at 512^2, forward + adjoint")
+        w3 = phantoms.c3(512, 512)
+        v3 = torch.from_numpy(w3.vol).to(dev)
+        k3 = torch.from_numpy(w3.tf_knots).to(dev)
+        tf3 = torch.from_numpy(w3.tf_rgba).to(dev)
+        tgt_tf = torch.from_numpy(w3.extra["target_tf_rgba"]).to(dev)
+        c3 = [dvr.camera_struct(c) for c in w3.cams]
+        f3 = dvr.features(v3, w3.spacing, w3.sigmas, c=w3.c)
+        target, _, _ = dvr.render(v3, f3, k3, tgt_tf, w3.params, c3, want_state=False)
+        times = []
+        for it in range(8):
+            a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+            a.record(stream)
+            im, T3, kl3 = dvr.render(v3, f3, k3, tf3, w3.params, c3)
+            b.record(stream)
+            dvr.render_backward(v3, f3, k3, tf3, w3.params, c3, T3, kl3, im - target)
+            c.record(stream)
+            torch.cuda.synchronize()
+            if it >= 2:
+                times.append((a.elapsed_time(b), b.elapsed_time(c)))
+        fw = float(np.median([t[0] for t in times]))
+        bw = float(np.median([t[1] for t in times]))
+        comps.update({"fwd_bwd_ms_per_view": (fw + bw) / len(c3), "fwd_ms_per_view": fw / len(c3),
+                      "bwd_ms_per_view": bw / len(c3), "fwd_bwd_workload": "128^3 phantom, 8 ortho views 512^2, 16-knot TF"})
+        log(f"fwd+bwd {comps['fwd_bwd_ms_per_view']:.3f} ms/view (fwd {fw / 8:.3f}, bwd {bw / 8:.3f})")
+
+    if args.copy_calibration:
+        src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+
+    # ------------------------------------------------------------------ CPU baseline (oracle)
+    cpu = None
+    if not args.no_cpu_baseline:
+        import oracle
+
+        log("CPU baseline: FP64 oracle, full feature pass + 65536 pixels of 2 views")
+        threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
+        sp = tuple(float(np.float32(h)) for h in w.spacing)
+        prm = {k: float(np.float32(v)) for k, v in w.params.items()}
+        v64 = w.vol.astype(np.float64)
+        t = time.perf_counter()
+        of = oracle.features(v64, sp, [float(np.float32(s)) for s in w.sigmas], c=float(np.float32(w.c)))
+        t_cf = time.perf_counter() - t
+        rng = np.random.default_rng(1)
+        M = 65536
+        pix = np.stack([rng.integers(0, 2, M), rng.integers(0, 1024, M), rng.integers(0, 1024, M)], 1).astype(np.int32)
+        t = time.perf_counter()
+        ro = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, [w.cams[0], w.cams[V // 4]], pix=pix)
+        t_cr = time.perf_counter() - t
+        s_per_sample = t_cr / max(ro["nsamp"], 1)
+        t_cpu_step = t_cf + s_per_sample * evaluated
+        cpu = {"value": evaluated / t_cpu_step, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
+               "sample": f"FP64 oracle: full 3-scale feature pass ({t_cf:.2f} s) + {M} random pixels of 2 of the "
+                         f"{V} views ({ro['nsamp']} samples, {t_cr:.2f} s); step time = features + per-sample "
+                         f"time x the step's {evaluated} evaluated samples",
+               "features_voxels_per_s": nvox / t_cf, "render_samples_per_s": ro["nsamp"] / t_cr}
+        log(f"CPU baseline {cpu['value']:.4g} samples/s on {threads} threads")
+
+    out = {"metric": METRIC, "value": samples_per_s, "unit": "ray-samples/s", "n_gpus": 1, "steps": K,
+           "warmup": args.warmup, "ms_per_step": 1e3 * t_step / K, "higher_is_better": True, "scaling": "weak",
+           "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+           "config": {"workload": f"head phantom {nx}x{ny}x{nz} FP32 at 1 mm with 24 vessel tubes and 3% Rician "
+                                  f"noise; features at sigma {{1,2,3}} mm; {V} perspective orbit views at 1024^2, "
+                                  f"step 0.5 voxel, 8-knot TF, early termination 0.99",
+                      "voxels": nvox, "views": V, "image": [1024, 1024]},
+           "roofline": roofline, "cpu_baseline": cpu, "components": comps}
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

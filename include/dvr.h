@@ -1,0 +1,176 @@
+/*
+ * dvr.h -- C ABI of the MI355X (gfx950) direct-volume-rendering hot path.
+ *
+ * Method: Beckley, "Decentralized Direct Volume Rendering: A Browser-Native GPU Architecture
+ * for MRI Digital Twins in Resource-Constrained Settings".  Two data-parallel passes:
+ *   features  per-voxel morphology: central-difference gradient (Sec. 2.3 Eq. 2), Gaussian-scale
+ *             Hessian and its eigenvalues, directional curvature k = g^T H g / g^T g (Sec. 2.3
+ *             Eq. 3) and multi-scale vesselness (Sec. 1, Frangi et al. 1998);
+ *   render    single-pass front-to-back raymarch: morphologically modulated opacity (Sec. 2.4
+ *             Eq. 4) and emission-absorption compositing (Sec. 2.4 Eq. 5-6);
+ * plus min-max normalization (Sec. 2.2 Eq. 1), the adjoint of the raymarch, and a batched
+ * launch of many volumes and views.
+ *
+ * Conventions (every entry point):
+ *   - Volumes are C order [nz][ny][nx] (x fastest); voxel (i,j,k) sits at (i hx, j hy, k hz) mm.
+ *     Every axis has n >= 2 and spacing h > 0.
+ *   - Pointers documented as "device" are device pointers, 16-byte aligned, owned by the caller;
+ *     structs passed by pointer are host memory and are read before the call returns.
+ *   - Calls are asynchronous and ordered on the given HIP stream (NULL = default stream).
+ *     Nothing synchronizes the device.  Scalars produced on the device (|grad I|_max) stay there.
+ *   - Arguments are validated before anything is enqueued: on a non-OK return nothing was
+ *     enqueued and dvr_last_error() describes the problem.  No exception crosses the ABI.
+ *   - Outputs are overwritten, never accumulated.
+ *   - The transfer function lives in device memory (the analogue of the paper's uniform buffers,
+ *     Sec. 4): editing it needs no re-launch setup, and the batched plan picks up the change.
+ */
+#ifndef DVR_H
+#define DVR_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#include <hip/hip_runtime_api.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum dvr_status {
+    DVR_OK = 0,
+    DVR_E_INVALID_ARG = -1, /* bad size, spacing, scale, parameter value */
+    DVR_E_NULL = -2,        /* a required pointer is NULL */
+    DVR_E_ALIGN = -3,       /* a device pointer is not 16-byte aligned */
+    DVR_E_UNSUPPORTED = -4, /* valid but not implemented combination (dtype/layout) */
+    DVR_E_NOMEM = -5,       /* host allocation failed (batched plans only) */
+    DVR_E_DEVICE = -6,      /* a HIP runtime call failed */
+    DVR_E_TIMEOUT = -8,     /* the batched launch's bounded dependency wait expired */
+    DVR_E_WORKSPACE = -9    /* workspace missing or smaller than the queried size */
+} dvr_status;
+
+typedef enum dvr_dtype { DVR_F32 = 0, DVR_F16 = 1, DVR_U16 = 2 } dvr_dtype;
+
+/* Feature storage layout.
+ *   DVR_PLANAR:       grad = [3][nz][ny][nx] (gx, gy, gz planes), kappa = [nz][ny][nx],
+ *                     ves = [nz][ny][nx], each of the buffer's dtype.
+ *   DVR_INTERLEAVED:  grad = one record of 8 values per voxel, [nz][ny][nx][8] =
+ *                     (I, gx, gy, gz, kappa, V, 0, 0) of the buffer's dtype (32 B in F32, 16 B in
+ *                     F16); kappa and ves are unused.  The record carries the intensity so that the
+ *                     raymarcher fetches one record per corner. */
+typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1 } dvr_layout;
+
+typedef struct dvr_grid {
+    int32_t nx, ny, nz; /* >= 2 each, nx*ny*nz < 2^31 */
+    float hx, hy, hz;   /* voxel spacing in mm, > 0 */
+} dvr_grid;
+
+#define DVR_MAX_SIGMA 8
+#define DVR_MAX_RADIUS 14 /* Gaussian radius floor(3 sigma/h + 1/2) per axis must not exceed this */
+
+typedef struct dvr_feature_params {
+    int32_t nsigma;                 /* 1..DVR_MAX_SIGMA scales; sigma_mm[0] also defines the Hessian of k */
+    float sigma_mm[DVR_MAX_SIGMA];  /* Gaussian scales in mm (per-axis sigma in voxels = sigma / h) */
+    float alpha, beta;              /* Frangi plate/blob sensitivities (> 0); 0.5, 0.5 is customary */
+    float c;                        /* Frangi structure sensitivity; <= 0 selects c = 1/2 max |sigma^2 H|_F */
+    float eig_gap_fp64;             /* eigenvalues whose smallest gap is below eig_gap_fp64 * max|lambda|
+                                       are re-solved in FP64; 0 disables the FP64 path */
+} dvr_feature_params;
+
+typedef struct dvr_features_buf {
+    void *grad;   /* device; see dvr_layout */
+    void *kappa;  /* device, PLANAR only */
+    void *ves;    /* device, PLANAR only */
+    float *gmax;  /* device scalar: max over voxels of |grad I|_2 (the |grad I|_max of Eq. 4) */
+    int32_t dtype;  /* DVR_F32 or DVR_F16 (storage type; arithmetic is FP32) */
+    int32_t layout; /* dvr_layout */
+} dvr_features_buf;
+
+typedef struct dvr_tf {
+    int32_t K;          /* 2..64 knots */
+    const float *knots; /* device [K], strictly increasing intensities */
+    const float *rgba;  /* device [K][4]: R, G, B in [0,1] (not premultiplied); A = extinction per mm >= 0 */
+} dvr_tf;
+
+typedef struct dvr_render_params {
+    float lambda_g; /* weight of the edge-strength factor |g|/|g|_max in Eq. 4, in [0,1] */
+    float lambda_k; /* weight of the curvature factor w(k) = |k| / (|k| + kappa0), in [0,1] */
+    float kappa0;   /* curvature half-saturation in 1/mm^2, > 0 */
+    float lambda_v; /* vesselness emphasis u = 1 + lambda_v V, >= 0 */
+    float step_vox; /* segment length as a fraction of min(h), >= 1/64 */
+    float et_alpha; /* early termination once accumulated opacity >= et_alpha; <= 0 disables it */
+} dvr_render_params;
+
+/* Camera, pixel (i, j) with row j = 0 at the top:
+ *   orthographic (persp = 0): origin o + (i+1/2) du + (j+1/2) dv, direction d0 (unit length);
+ *   perspective  (persp = 1): origin o, direction normalize(d0 + (i+1/2) du + (j+1/2) dv). */
+typedef struct dvr_camera {
+    int32_t persp, width, height;
+    float o[3], d0[3], du[3], dv[3];
+} dvr_camera;
+
+/* Per-ray state the forward pass leaves for the adjoint: the transmittance before the last
+ * evaluated sample and that sample's index (-1 for a ray that misses the volume). */
+typedef struct dvr_ray_state {
+    float *T_last;      /* device [ncam][H][W] */
+    int32_t *k_last;    /* device [ncam][H][W] */
+    uint64_t *counters; /* device [2], nullable; dvr_render overwrites it with the number of evaluated
+                           samples and of those with non-zero extinction (the rest are exactly
+                           transparent and skip the feature fetch) */
+} dvr_ray_state;
+
+/* Library version, for the binding's load check. */
+int32_t dvr_version(void);
+
+/* Thread-local message of the last non-OK status returned on this thread. */
+const char *dvr_last_error(void);
+
+/* Eq. 1 (Sec. 2.2): out = (raw - min) / (max - min) over all n values, 0 where max == min.
+ * raw: device, DVR_U16 or DVR_F32 or DVR_F16; out: device, DVR_F16 (round to nearest even) or
+ * DVR_F32.  ws: device workspace of at least dvr_normalize_workspace() bytes. */
+dvr_status dvr_normalize_workspace(int64_t n, size_t *bytes);
+dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t out_dtype, int64_t n,
+                         void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Feature pass (Sec. 2.3 Eq. 2-3; Sec. 1 multi-scale Hessian and vesselness).
+ *   gradient  g_a = (I[a+1] - I[a-1]) / (2 h_a), indices clamped to the grid (Eq. 2);
+ *   gmax      max |g|_2 over all voxels, written to out->gmax;
+ *   Hessian   of the volume smoothed with the sampled, normalized Gaussian of radius
+ *             floor(3 sigma/h + 1/2) (clamped indices), by central second differences (clamped);
+ *             computed as derivative-of-Gaussian filters, which is the same linear operator;
+ *   kappa     g^T H g / g^T g with H at sigma_mm[0] (units I/mm^2); 0 where g = 0 (Eq. 3);
+ *   V         max over scales of Frangi's bright-tube vesselness of the magnitude-sorted
+ *             eigenvalues of sigma^2 H (0 unless lambda2 < 0 and lambda3 < 0).
+ * vol: device [nz][ny][nx] of vol_dtype (DVR_F32 or DVR_F16).  ws: device workspace of at least
+ * dvr_features_workspace() bytes.  out: see dvr_features_buf (F32 or F16, PLANAR or INTERLEAVED). */
+dvr_status dvr_features_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes);
+dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_feature_params *fp,
+                        const dvr_features_buf *out, void *ws, size_t ws_bytes, hipStream_t stream);
+
+/* Raymarch (Sec. 2.4 Eq. 4-6), one ray per pixel of each camera.  The box [0,(n-1)h] is clipped
+ * by the slab method; the chord [tn, tf] is cut into N = ceil(L / delta) segments of
+ * delta = step_vox * min(h) (the last one shorter) and sampled at segment midpoints.  Each sample
+ * trilinearly interpolates I, g, kappa, V; the TF (piecewise linear, clamped) gives colour c and
+ * extinction tau; sigma = tau * m * w * u with m = (1 - lambda_g) + lambda_g min(|g|/gmax, 1),
+ * w = (1 - lambda_k) + lambda_k |k| / (|k| + kappa0), u = 1 + lambda_v V; alpha = 1 - exp(-sigma
+ * delta_k); C += T alpha c, T *= 1 - alpha (Eq. 5-6 in transmittance form), A = 1 - T.
+ * rgba: device [ncam][H][W][4] float (premultiplied R, G, B and A).  All cameras must share W and
+ * H.  state: nullable; filled for dvr_render_backward.  Without early termination a ray still
+ * stops once T <= 2^-24 (the light left is below FP32 resolution). */
+dvr_status dvr_render(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_features_buf *feat,
+                      const dvr_tf *tf, const dvr_render_params *rp, const dvr_camera *cams, int32_t ncam,
+                      float *rgba, const dvr_ray_state *state, hipStream_t stream);
+
+/* Adjoint of dvr_render with respect to the TF values and the voxel intensities; the features
+ * are held constant.  Each ray is walked back to front from the stored (T_last, k_last),
+ * recomputing every sample exactly as the forward pass did.
+ * dL_drgba: device [ncam][H][W][4]; dL_dtf: device [K][4] float, overwritten;
+ * dL_dvol: device [nz][ny][nx] float, overwritten, nullable. */
+dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                               const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
+                               const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
+                               const float *dL_drgba, float *dL_dtf, float *dL_dvol, hipStream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DVR_H */

@@ -1,0 +1,230 @@
+"""MI355X (gfx950) hot path of the direct-volume-rendering method of Beckley, "Decentralized Direct
+Volume Rendering: A Browser-Native GPU Architecture for MRI Digital Twins in Resource-Constrained
+Settings": the per-voxel morphology pass (Sec. 2.3 Eq. 2-3, Sec. 1 multi-scale Hessian and
+vesselness) and the front-to-back raymarcher (Sec. 2.4 Eq. 4-6), with its adjoint.
+
+The Python layer is a thin binding: PyTorch supplies device memory and the current stream, and
+every arithmetic step runs in the HIP kernels of libdvr.so (see include/dvr.h).
+"""
+from __future__ import annotations
+
+import ctypes as C
+from dataclasses import dataclass
+
+import torch
+
+from . import _abi as abi
+from ._abi import DVRError
+
+__all__ = ["Features", "features", "render", "render_backward", "normalize", "DVRRender", "DVRError",
+           "camera_struct", "lib"]
+
+
+def lib():
+    return abi.load()
+
+
+def _stream():
+    return C.c_void_p(torch.cuda.current_stream().cuda_stream)
+
+
+def _dt(t: torch.Tensor) -> int:
+    if t.dtype == torch.float32:
+        return abi.DVR_F32
+    if t.dtype == torch.float16:
+        return abi.DVR_F16
+    if t.dtype in (torch.uint16, torch.int16):
+        return abi.DVR_U16
+    raise TypeError(f"unsupported dtype {t.dtype}")
+
+
+def _ptr(t):
+    return None if t is None else C.c_void_p(t.data_ptr())
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors must be contiguous CUDA (HIP) tensors")
+
+
+def grid_struct(shape_zyx, spacing):
+    nz, ny, nx = shape_zyx
+    return abi.Grid(int(nx), int(ny), int(nz), float(spacing[0]), float(spacing[1]), float(spacing[2]))
+
+
+def camera_struct(cam):
+    """From any object with persp, width, height, o, d0, du, dv (e.g. phantoms.Camera)."""
+    c = abi.Camera()
+    c.persp, c.width, c.height = int(cam.persp), int(cam.width), int(cam.height)
+    for name in ("o", "d0", "du", "dv"):
+        arr = getattr(c, name)
+        v = getattr(cam, name)
+        for k in range(3):
+            arr[k] = float(v[k])
+    return c
+
+
+@dataclass
+class Features:
+    """Device-resident feature fields.  planar: grad [3][nz][ny][nx], kappa, ves [nz][ny][nx];
+    interleaved: grad [nz][ny][nx][8] = (I, gx, gy, gz, kappa, V, 0, 0); gmax: 1-element tensor."""
+    grad: torch.Tensor
+    kappa: torch.Tensor | None
+    ves: torch.Tensor | None
+    gmax: torch.Tensor
+    layout: int
+    shape: tuple
+    spacing: tuple
+
+    @property
+    def dtype(self):
+        return self.grad.dtype
+
+    def buf(self):
+        return abi.FeaturesBuf(self.grad.data_ptr(), self.kappa.data_ptr() if self.kappa is not None else None,
+                               self.ves.data_ptr() if self.ves is not None else None, self.gmax.data_ptr(),
+                               _dt(self.grad), self.layout)
+
+
+def _fparams(sigmas, alpha, beta, c, eig_gap):
+    fp = abi.FeatureParams()
+    if not 1 <= len(sigmas) <= abi.DVR_MAX_SIGMA:
+        raise ValueError("1..8 scales")
+    fp.nsigma = len(sigmas)
+    for i, s in enumerate(sigmas):
+        fp.sigma_mm[i] = float(s)
+    fp.alpha, fp.beta, fp.c, fp.eig_gap_fp64 = float(alpha), float(beta), float(c), float(eig_gap)
+    return fp
+
+
+def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANAR, device="cuda"):
+    nz, ny, nx = shape_zyx
+    if layout == abi.DVR_PLANAR:
+        grad = torch.empty((3, nz, ny, nx), dtype=dtype, device=device)
+        kappa = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+        ves = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+    else:
+        grad = torch.empty((nz, ny, nx, 8), dtype=dtype, device=device)
+        kappa = ves = None
+    gmax = torch.empty(1, dtype=torch.float32, device=device)
+    return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing))
+
+
+def features_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2):
+    n = C.c_size_t()
+    abi.check(lib().dvr_features_workspace(C.byref(grid_struct(shape_zyx, spacing)),
+                                           C.byref(_fparams(sigmas, alpha, beta, c, eig_gap)), C.byref(n)))
+    return n.value
+
+
+def features(vol, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2, dtype=None, layout=abi.DVR_PLANAR,
+             out=None, ws=None):
+    """Feature pass (dvr_features): gradient, |grad I|_max, k and vesselness of vol [nz][ny][nx]."""
+    _require_cuda(vol)
+    dtype = vol.dtype if dtype is None else dtype
+    g = grid_struct(vol.shape, spacing)
+    fp = _fparams(sigmas, alpha, beta, c, eig_gap)
+    out = alloc_features(tuple(vol.shape), spacing, dtype, layout, vol.device) if out is None else out
+    nbytes = features_workspace_bytes(tuple(vol.shape), spacing, sigmas, alpha, beta, c, eig_gap)
+    if ws is None or ws.numel() < nbytes:
+        ws = torch.empty(nbytes, dtype=torch.uint8, device=vol.device)
+    fb = out.buf()
+    abi.check(lib().dvr_features(_ptr(vol), _dt(vol), C.byref(g), C.byref(fp), C.byref(fb), _ptr(ws), nbytes,
+                                 _stream()))
+    return out
+
+
+def _tf_struct(knots, rgba):
+    _require_cuda(knots, rgba)
+    if knots.dtype != torch.float32 or rgba.dtype != torch.float32:
+        raise TypeError("TF knots and rgba are float32")
+    return abi.TF(int(knots.numel()), knots.data_ptr(), rgba.data_ptr())
+
+
+def _rparams(p):
+    return abi.RenderParams(float(p["lambda_g"]), float(p["lambda_k"]), float(p["kappa0"]), float(p["lambda_v"]),
+                            float(p["step_vox"]), float(p["et_alpha"]))
+
+
+def _cams(cams):
+    arr = (abi.Camera * len(cams))()
+    for i, c in enumerate(cams):
+        arr[i] = c if isinstance(c, abi.Camera) else camera_struct(c)
+    return arr
+
+
+def render(vol, feats: Features, knots, rgba, params, cams, want_state=True, out=None, counters=None):
+    """dvr_render: returns (rgba [ncam][H][W][4], T_last, k_last) (state tensors None if not wanted).
+    counters: optional int64 device tensor [2] overwritten with (evaluated, shaded) sample counts."""
+    _require_cuda(vol)
+    carr = _cams(cams)
+    W, H = carr[0].width, carr[0].height
+    n = len(cams)
+    dev = feats.grad.device
+    img = torch.empty((n, H, W, 4), dtype=torch.float32, device=dev) if out is None else out
+    T_last = k_last = None
+    st = None
+    if want_state:
+        T_last = torch.empty((n, H, W), dtype=torch.float32, device=dev)
+        k_last = torch.empty((n, H, W), dtype=torch.int32, device=dev)
+        st = abi.RayState(T_last.data_ptr(), k_last.data_ptr(),
+                          counters.data_ptr() if counters is not None else None)
+    g = grid_struct(feats.shape, feats.spacing)
+    fb = feats.buf()
+    tf = _tf_struct(knots, rgba)
+    rp = _rparams(params)
+    abi.check(lib().dvr_render(_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g), C.byref(fb),
+                               C.byref(tf), C.byref(rp), carr, n, _ptr(img), C.byref(st) if st else None, _stream()))
+    return img, T_last, k_last
+
+
+def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_last, dout, want_dvol=True):
+    """dvr_render_backward: returns (dL/dTF [K][4], dL/dvol [nz][ny][nx] or None)."""
+    carr = _cams(cams)
+    dev = feats.grad.device
+    dtf = torch.empty((knots.numel(), 4), dtype=torch.float32, device=dev)
+    dvol = torch.empty(feats.shape, dtype=torch.float32, device=dev) if want_dvol else None
+    dout = dout.contiguous().float()
+    g = grid_struct(feats.shape, feats.spacing)
+    fb = feats.buf()
+    tf = _tf_struct(knots, rgba)
+    rp = _rparams(params)
+    st = abi.RayState(T_last.data_ptr(), k_last.data_ptr(), None)
+    abi.check(lib().dvr_render_backward(_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g),
+                                        C.byref(fb), C.byref(tf), C.byref(rp), carr, len(cams), C.byref(st),
+                                        _ptr(dout), _ptr(dtf), _ptr(dvol), _stream()))
+    return dtf, dvol
+
+
+def normalize(raw, out_dtype=torch.float16):
+    """dvr_normalize (Eq. 1) of a device tensor (uint16 counts, float32 or float16)."""
+    _require_cuda(raw)
+    out = torch.empty(raw.shape, dtype=out_dtype, device=raw.device)
+    n = C.c_size_t()
+    abi.check(lib().dvr_normalize_workspace(raw.numel(), C.byref(n)))
+    ws = torch.empty(max(n.value, 256), dtype=torch.uint8, device=raw.device)
+    abi.check(lib().dvr_normalize(_ptr(raw), _dt(raw), _ptr(out), _dt(out), raw.numel(), _ptr(ws), n.value,
+                                  _stream()))
+    return out
+
+
+class DVRRender(torch.autograd.Function):
+    """rgba = render(vol, TF values) with gradients for the voxel intensities and the TF values
+    (knot positions, gradient, k and V are held constant).  The backward is the hand-written adjoint
+    raymarch, which recomputes the samples from the stored per-ray (T_last, k_last)."""
+
+    @staticmethod
+    def forward(ctx, vol, tf_rgba, feats, knots, params, cams):
+        img, T_last, k_last = render(vol, feats, knots, tf_rgba.contiguous(), params, cams, want_state=True)
+        ctx.save_for_backward(vol, tf_rgba, knots, T_last, k_last)
+        ctx.feats, ctx.params, ctx.cams = feats, params, cams
+        return img
+
+    @staticmethod
+    def backward(ctx, dimg):
+        vol, tf_rgba, knots, T_last, k_last = ctx.saved_tensors
+        dtf, dvol = render_backward(vol, ctx.feats, knots, tf_rgba.contiguous(), ctx.params, ctx.cams, T_last,
+                                    k_last, dimg, want_dvol=ctx.needs_input_grad[0])
+        return (dvol if ctx.needs_input_grad[0] else None, dtf if ctx.needs_input_grad[1] else None,
+                None, None, None, None)

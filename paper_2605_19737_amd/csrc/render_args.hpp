@@ -1,0 +1,63 @@
+// Kernel-argument records of the raymarcher (passed by value; no device-side parameter buffers,
+// so a launch records into a HIP graph with nothing else to copy).
+#pragma once
+
+#include <stdint.h>
+
+#include "dvr.h"
+
+namespace dvr {
+
+constexpr int kCamChunk = 32;  // cameras per launch (kernel arguments stay under 4 KB)
+
+struct KCam {
+    int32_t persp;
+    float o[3], d0[3], du[3], dv[3];
+};
+
+struct KFeat {
+    const void *vol;  // planar: the intensity volume (same dtype as the features)
+    const void *grad, *kappa, *ves;
+    const float *gmax;
+    int32_t dtype, layout;
+};
+
+struct KGrid {
+    int32_t n[3];
+    double h[3];
+    double delta;  // step_vox * min(h), mm
+};
+
+struct KTF {
+    int32_t K;
+    const float *knots, *rgba;
+};
+
+struct KRender {
+    float lg, omlg, lk, omlk, k0, lv;
+    float Tstop;  // stop once T <= Tstop (1 - et_alpha, or 2^-24 without early termination)
+};
+
+struct KLaunch {
+    int32_t W, H, ncam, cam_base;
+    float *out;             // [cam][H][W][4]
+    float *T_last;          // [cam][H][W] or null
+    int32_t *k_last;        // [cam][H][W] or null
+    const float *dout;      // backward: dL/d rgba
+    float *dtf;             // backward: dL/d TF values [K][4]
+    float *dvol;            // backward: dL/d I [N] or null
+    unsigned long long *counters;  // forward: evaluated samples, shaded samples (or null)
+    KCam cams[kCamChunk];
+};
+
+struct RenderArgs {
+    KFeat feat;
+    KGrid grid;
+    KTF tf;
+    KRender rp;
+    KLaunch launch;  // template: cams filled per chunk
+    const KCam *cams;
+    int32_t ncam;
+};
+
+}  // namespace dvr

@@ -213,12 +213,12 @@ def tf_head():
     rgba = np.array([
         [0.0, 0.0, 0.0, 0.0],
         [0.0, 0.0, 0.0, 0.0],
-        [0.3, 0.5, 1.0, 0.01],
-        [0.9, 0.6, 0.5, 0.03],
-        [1.0, 0.95, 0.85, 0.06],
-        [0.9, 0.9, 0.8, 0.02],
-        [0.8, 0.2, 0.1, 0.05],
-        [1.0, 0.1, 0.1, 0.4]], np.float32)
+        [0.3, 0.5, 1.0, 0.08],
+        [0.9, 0.6, 0.5, 0.25],
+        [1.0, 0.95, 0.85, 0.5],
+        [0.9, 0.9, 0.8, 0.15],
+        [0.8, 0.2, 0.1, 0.4],
+        [1.0, 0.1, 0.1, 3.0]], np.float32)
     return knots, rgba
 
 
@@ -293,7 +293,7 @@ def c2(width=1024, height=1024, views=None, nviews=360):
     views = range(nviews) if views is None else views
     cams = [persp_camera(dims, h, float(v), 15.0, width, height) for v in views]
     return Workload("c2", vol, h, [1.0, 2.0, 3.0], c=0.25, tf_knots=knots, tf_rgba=rgba,
-                    params=render_params(lambda_v=2.0, et_alpha=0.99), cams=cams)
+                    params=render_params(lambda_g=0.5, lambda_v=2.0, et_alpha=0.99), cams=cams)
 
 
 def c3(width=512, height=512, views=None):
@@ -368,7 +368,7 @@ def c5(width=2048, height=2048, views=None, dims=(512, 512, 400), spacing=(0.5, 
     views = range(8) if views is None else views
     cams = [ortho_camera(dims, h, 45.0 * k, 20.0, width, height) for k in views]
     return Workload("c5", raw, h, [0.5], c=0.25, tf_knots=knots, tf_rgba=rgba,
-                    params=render_params(lambda_v=2.0, et_alpha=0.99), cams=cams,
+                    params=render_params(lambda_g=0.5, lambda_v=2.0, et_alpha=0.99), cams=cams,
                     extra=dict(target_tf_rgba=target_rgba))
 
 

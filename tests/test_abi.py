@@ -1,0 +1,166 @@
+"""CPU checks of the C ABI: libdvr.so loads, exports every function include/dvr.h declares, and
+rejects bad arguments before enqueueing anything (these calls never reach the GPU: validation fails
+first, and the fake device pointers below are never dereferenced)."""
+import ctypes as C
+import os
+import subprocess
+
+import pytest
+
+from paper_2605_19737_amd import _abi as abi
+
+FAKE = 0x10000  # 16-byte aligned, never dereferenced
+
+
+@pytest.fixture(scope="module")
+def L():
+    return abi.load()
+
+
+def test_exports_every_declared_symbol(L):
+    names = abi.declared_functions()
+    assert len(names) >= 8
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    out = subprocess.run(["nm", "-D", "--defined-only", abi.LIB_PATH], capture_output=True, text=True).stdout
+    for n in names:
+        assert f" T {n}" in out, n
+    assert L.dvr_version() == 1
+
+
+def _grid(nx=8, ny=9, nz=10, h=(1.0, 1.0, 1.0)):
+    return abi.Grid(nx, ny, nz, *h)
+
+
+def _fp(sig=(1.0,), c=0.1):
+    fp = abi.FeatureParams()
+    fp.nsigma = len(sig)
+    for i, s in enumerate(sig):
+        fp.sigma_mm[i] = s
+    fp.alpha, fp.beta, fp.c, fp.eig_gap_fp64 = 0.5, 0.5, c, 1e-2
+    return fp
+
+
+def _fb(dtype=abi.DVR_F32, layout=abi.DVR_PLANAR):
+    return abi.FeaturesBuf(FAKE, FAKE, FAKE, FAKE, dtype, layout)
+
+
+def _status(L, name, *args):
+    s = getattr(L, name)(*args)
+    return s, L.dvr_last_error().decode()
+
+
+def test_workspace_query(L):
+    n = C.c_size_t()
+    assert L.dvr_features_workspace(C.byref(_grid()), C.byref(_fp()), C.byref(n)) == 0
+    assert n.value == 256 + 12 * 8 * 9 * 10
+    assert L.dvr_normalize_workspace(100, C.byref(n)) == 0 and n.value >= 8
+
+
+@pytest.mark.parametrize("grid,fp,code", [
+    (_grid(1, 9, 10), _fp(), abi.STATUS and -1),
+    (_grid(h=(1.0, 0.0, 1.0)), _fp(), -1),
+    (_grid(h=(1.0, float("nan"), 1.0)), _fp(), -1),
+    (_grid(), _fp(sig=()), -1),
+    (_grid(), _fp(sig=(-1.0,)), -1),
+    (_grid(), _fp(sig=(40.0,)), -1),          # radius beyond the limit
+    (_grid(4000, 4000, 10), _fp(), -1),       # beyond 32-bit addressing
+])
+def test_features_rejects_bad_params(L, grid, fp, code):
+    s, msg = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(grid), C.byref(fp),
+                     C.byref(_fb()), C.c_void_p(FAKE), 1 << 30, None)
+    assert s == code and msg
+
+
+def test_features_rejects_null_align_workspace(L):
+    g, fp = _grid(), _fp()
+    s, _ = _status(L, "dvr_features", None, abi.DVR_F32, C.byref(g), C.byref(fp), C.byref(_fb()), C.c_void_p(FAKE),
+                   1 << 30, None)
+    assert s == -2
+    s, _ = _status(L, "dvr_features", C.c_void_p(FAKE + 4), abi.DVR_F32, C.byref(g), C.byref(fp), C.byref(_fb()),
+                   C.c_void_p(FAKE), 1 << 30, None)
+    assert s == -3
+    s, msg = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(g), C.byref(fp), C.byref(_fb()),
+                     C.c_void_p(FAKE), 64, None)
+    assert s == -9 and "workspace" in msg
+    s, _ = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_U16, C.byref(g), C.byref(fp), C.byref(_fb()),
+                   C.c_void_p(FAKE), 1 << 30, None)
+    assert s == -4
+    bad = abi.FeaturesBuf(FAKE, None, FAKE, FAKE, abi.DVR_F32, abi.DVR_PLANAR)
+    s, _ = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(g), C.byref(fp), C.byref(bad),
+                   C.c_void_p(FAKE), 1 << 30, None)
+    assert s == -2
+    s, _ = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, None, C.byref(fp), C.byref(_fb()),
+                   C.c_void_p(FAKE), 1 << 30, None)
+    assert s == -2
+
+
+def _cam(w=4, h=4, persp=0):
+    c = abi.Camera()
+    c.persp, c.width, c.height = persp, w, h
+    for k in range(3):
+        c.o[k], c.d0[k], c.du[k], c.dv[k] = -1.0, 0.0, 0.0, 0.0
+    c.d0[2] = 1.0
+    c.du[0] = c.dv[1] = 0.5
+    return c
+
+
+def _rp(**kw):
+    p = dict(lambda_g=1.0, lambda_k=0.5, kappa0=0.05, lambda_v=0.0, step_vox=0.5, et_alpha=0.0)
+    p.update(kw)
+    return abi.RenderParams(*[p[k] for k in ("lambda_g", "lambda_k", "kappa0", "lambda_v", "step_vox", "et_alpha")])
+
+
+@pytest.mark.parametrize("tf_K,rp,cams,code", [
+    (1, _rp(), [_cam()], -1),
+    (65, _rp(), [_cam()], -1),
+    (4, _rp(lambda_g=1.5), [_cam()], -1),
+    (4, _rp(kappa0=0.0), [_cam()], -1),
+    (4, _rp(step_vox=0.0), [_cam()], -1),
+    (4, _rp(step_vox=0.01), [_cam()], -1),
+    (4, _rp(et_alpha=1.0), [_cam()], -1),
+    (4, _rp(), [_cam(4, 4), _cam(4, 5)], -1),
+    (4, _rp(), [_cam(persp=2)], -1),
+    (4, _rp(), [_cam(0, 4)], -1),
+])
+def test_render_rejects_bad_params(L, tf_K, rp, cams, code):
+    arr = (abi.Camera * len(cams))(*cams)
+    tf = abi.TF(tf_K, FAKE, FAKE)
+    s, msg = _status(L, "dvr_render", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fb()), C.byref(tf),
+                     C.byref(rp), arr, len(cams), C.c_void_p(FAKE), None, None)
+    assert s == code and msg
+
+
+def test_render_rejects_dtype_mismatch_and_missing_state(L):
+    arr = (abi.Camera * 1)(_cam())
+    tf = abi.TF(4, FAKE, FAKE)
+    s, _ = _status(L, "dvr_render", C.c_void_p(FAKE), abi.DVR_F16, C.byref(_grid()), C.byref(_fb()), C.byref(tf),
+                   C.byref(_rp()), arr, 1, C.c_void_p(FAKE), None, None)
+    assert s == -4
+    s, _ = _status(L, "dvr_render_backward", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fb()),
+                   C.byref(tf), C.byref(_rp()), arr, 1, None, C.c_void_p(FAKE), C.c_void_p(FAKE), None, None)
+    assert s == -2
+    st = abi.RayState(FAKE, FAKE, None)
+    s, _ = _status(L, "dvr_render_backward", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fb()),
+                   C.byref(tf), C.byref(_rp()), arr, 1, C.byref(st), None, C.c_void_p(FAKE), None, None)
+    assert s == -2
+
+
+def test_normalize_rejects(L):
+    s, _ = _status(L, "dvr_normalize", C.c_void_p(FAKE), 7, C.c_void_p(FAKE), abi.DVR_F16, 10, C.c_void_p(FAKE), 256,
+                   None)
+    assert s == -4
+    s, _ = _status(L, "dvr_normalize", C.c_void_p(FAKE), abi.DVR_U16, C.c_void_p(FAKE), abi.DVR_F16, 0,
+                   C.c_void_p(FAKE), 256, None)
+    assert s == -1
+    s, _ = _status(L, "dvr_normalize", C.c_void_p(FAKE), abi.DVR_U16, C.c_void_p(FAKE), abi.DVR_F16, 10,
+                   C.c_void_p(FAKE), 8, None)
+    assert s == -9
+
+
+def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
+    """No CPU fallback: a missing libdvr.so is an ImportError, not a silent substitute."""
+    monkeypatch.setattr(abi, "LIB_PATH", os.path.join(str(tmp_path), "missing.so"))
+    monkeypatch.setattr(abi, "_lib", None)
+    with pytest.raises(ImportError):
+        abi.load()

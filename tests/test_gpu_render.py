@@ -1,0 +1,286 @@
+"""GPU parity of the raymarcher (dvr_render) and its adjoint (dvr_render_backward) against the
+FP64 oracle.
+
+Bar: each RGBA channel within max|gpu - oracle| / max|oracle| <= 1e-5 (FP32 features).  Rays
+whose oracle transmittance at the stop sample lies within 1e-5 (relative) of the early-termination
+threshold may legitimately take one sample more or less; they are excluded and counted.  Without
+early termination the GPU also stops once T <= 2^-24 (light left below FP32 resolution), so k_last
+is compared only on rays whose oracle T stays above 1e-6.  Adjoint: normwise relative error <= 1e-4
+against the oracle's reverse mode, whose own agreement with central finite differences is pinned
+on the CPU."""
+import math
+
+import numpy as np
+import pytest
+import torch
+
+import oracle
+import paper_2605_19737_amd as dvr
+import phantoms
+from paper_2605_19737_amd import _abi as abi
+from tests.gpu_common import f32, oracle_params, rel_err, sp32, tf_dev, to_dev
+
+pytestmark = pytest.mark.gpu
+TOL = 1e-5
+
+
+def _gpu_scene(w, layout=abi.DVR_PLANAR, dtype=torch.float32, sigmas=None):
+    dv = to_dev(w.vol, dtype)
+    f = dvr.features(dv, w.spacing, w.sigmas if sigmas is None else sigmas, c=w.c, dtype=dtype, layout=layout)
+    return dv, f
+
+
+def _oracle_feats(dv, w, sigmas=None):
+    return oracle.features(dv.float().cpu().numpy().astype(np.float64), sp32(w.spacing),
+                           [f32(s) for s in (w.sigmas if sigmas is None else sigmas)], c=f32(w.c))
+
+
+def _compare_images(got, T_got, k_got, ref, et, label, pix=None):
+    """Per-channel parity with the early-termination boundary exclusion."""
+    img = got.cpu().numpy().astype(np.float64)
+    Tg = T_got.cpu().numpy()
+    kg = k_got.cpu().numpy()
+    if pix is not None:
+        img = img[pix[:, 0], pix[:, 2], pix[:, 1]]
+        Tg = Tg[pix[:, 0], pix[:, 2], pix[:, 1]]
+        kg = kg[pix[:, 0], pix[:, 2], pix[:, 1]]
+    r = ref["rgba"].reshape(img.shape)
+    rk = ref["k_last"].reshape(kg.shape)
+    rT = ref["T_last"].reshape(Tg.shape)
+    excl = np.zeros(kg.shape, bool)
+    if et > 0:
+        # oracle T after the stop sample near 1 - et: either side is a correct stop
+        Tend = 1.0 - r[..., 3]
+        excl = np.abs(Tend - (1.0 - et)) <= 1e-5 * (1.0 - et)
+        excl |= np.abs(rT - (1.0 - et)) <= 1e-5 * (1.0 - et)
+    errs = [rel_err(img[..., ch][~excl], r[..., ch][~excl]) for ch in range(4)]
+    print(f"[render] {label}: err R={errs[0]:.2e} G={errs[1]:.2e} B={errs[2]:.2e} A={errs[3]:.2e} "
+          f"excluded={int(excl.sum())}/{excl.size}", flush=True)
+    assert excl.mean() < 1e-3
+    assert max(errs) <= TOL
+    keep = ~excl & ((1.0 - r[..., 3]) > 1e-6)
+    mism = (kg != rk) & keep
+    assert np.all(kg[rk < 0] == -1)
+    assert mism.sum() == 0, f"k_last differs on {int(mism.sum())} rays"
+
+
+def test_render_c1():
+    """256^2 orthographic view of the 64^3 phantom, 4-knot TF, all Eq. 4 factors, no ET."""
+    w = phantoms.c1()
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    of = _oracle_feats(dv, w)
+    ref = oracle.render(dv.cpu().numpy().astype(np.float64), of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                        oracle_params(w.params), w.cams)
+    _compare_images(img, T, k, ref, 0.0, "c1")
+    assert float(img[..., 3].max()) > 0.3
+
+
+def test_render_head_full_size_sampled():
+    """The benchmarked launch: 1024^2 perspective views of the head phantom with 3-scale features,
+    8-knot TF, early termination 0.99, rendered in one call; compared on 6000 sampled pixels."""
+    w = phantoms.c2(1024, 1024, views=[0, 37, 90, 200])
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    of = _oracle_feats(dv, w)
+    rng = np.random.default_rng(5)
+    M = 6000
+    pix = np.stack([rng.integers(0, 4, M), rng.integers(0, 1024, M), rng.integers(0, 1024, M)], 1).astype(np.int32)
+    ref = oracle.render(dv.cpu().numpy().astype(np.float64), of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                        oracle_params(w.params), w.cams, pix=pix)
+    _compare_images(img, T, k, ref, f32(w.params["et_alpha"]), "head 1024^2 persp", pix=pix)
+
+
+def test_render_head_small_full_image():
+    """Whole 96^2 perspective images of the head phantom (every pixel compared), ET on."""
+    w = phantoms.c2(96, 96, views=[15, 130])
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    of = _oracle_feats(dv, w)
+    ref = oracle.render(dv.cpu().numpy().astype(np.float64), of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                        oracle_params(w.params), w.cams)
+    _compare_images(img, T, k, ref, f32(w.params["et_alpha"]), "head 96^2")
+
+
+def test_render_anisotropic_batched_volume():
+    """Thick-slice volume (h_z 3-5 mm, sub-mm in-plane): delta = 0.5 min(h), ragged 50x70 image."""
+    w = phantoms.c4_volume(5, 50, 70, views=[0, 1])
+    w.cams = [phantoms.ortho_camera(w.dims, w.spacing, 90.0 * k + 10, 15.0, 50, 70) for k in range(2)]
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    of = _oracle_feats(dv, w)
+    ref = oracle.render(dv.cpu().numpy().astype(np.float64), of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                        oracle_params(w.params), w.cams)
+    _compare_images(img, T, k, ref, f32(w.params["et_alpha"]), "c4_5 50x70")
+
+
+def test_render_layouts_agree():
+    """Interleaved FP32 records hold the same values as the planar fields, and the image agrees to
+    FP32 rounding (the two instantiations may schedule the same sums differently)."""
+    w = phantoms.c1(64, 64)
+    dv, fp = _gpu_scene(w)
+    _, fi = _gpu_scene(w, layout=abi.DVR_INTERLEAVED)
+    kn, rg = tf_dev(w)
+    a = dvr.render(dv, fp, kn, rg, w.params, w.cams)
+    b = dvr.render(None, fi, kn, rg, w.params, w.cams)
+    d = (a[0] - b[0]).abs()
+    print(f"[layouts] max |planar - interleaved| = {float(d.max()):.3e}, differing pixels "
+          f"{int((d.amax(-1) > 0).sum())}/{d.shape[1] * d.shape[2]}, k_last differs "
+          f"{int((a[2] != b[2]).sum())}", flush=True)
+    assert float(d.max()) <= 1e-6 * float(a[0].abs().max())
+    assert int((a[2] != b[2]).sum()) == 0
+
+
+def test_render_edge_cases():
+    """A camera that misses the box (zero colour, k_last = -1), a 1x1 image, a 2x2x2 volume,
+    and a ray grazing the far face of the box along an axis."""
+    vol = phantoms.small_random(3, (2, 2, 2), lo=0.1, hi=0.9).astype(np.float32).astype(np.float64)
+    sp = (1.0, 1.0, 1.0)
+    dv = to_dev(vol)
+    f = dvr.features(dv, sp, [1.0], c=0.1)
+    knots = np.array([0.0, 0.5, 1.0], np.float32)
+    rgba = np.array([[0.2, 0.3, 0.4, 0.5], [0.9, 0.1, 0.2, 1.5], [0.3, 0.8, 0.5, 0.7]], np.float32)
+    prm = phantoms.render_params(lambda_g=0.3, lambda_k=0.2, lambda_v=0.5)
+    miss = phantoms.Camera(0, 3, 2, np.array([5, 5, -3], np.float32), np.array([0, 0, 1], np.float32),
+                           np.array([1, 0, 0], np.float32), np.array([0, 1, 0], np.float32))
+    one = phantoms.Camera(0, 3, 2, np.array([0.3, 0.4, -3], np.float32), np.array([0, 0, 1], np.float32),
+                          np.array([0.2, 0, 0], np.float32), np.array([0, 0.2, 0], np.float32))
+    graze = phantoms.Camera(0, 3, 2, np.array([1.0, 0.5, -1], np.float32), np.array([0, 0, 1], np.float32),
+                            np.array([0, 0, 0], np.float32), np.array([0, 0, 0], np.float32))
+    cams = [miss, one, graze]
+    img, T, k = dvr.render(dv, f, to_dev(knots), to_dev(rgba), prm, cams)
+    of = oracle.features(vol, sp, [1.0], c=0.1)
+    ref = oracle.render(vol, of, of["gmax"], sp, knots, rgba, oracle_params(prm), cams)
+    assert np.all(k[0].cpu().numpy() == -1) and float(img[0].abs().max()) == 0.0
+    _compare_images(img, T, k, ref, 0.0, "edge")
+    c1px = phantoms.Camera(1, 1, 1, np.array([0.5, 0.5, -2], np.float32), np.array([0, 0, 1], np.float32),
+                           np.array([0, 0, 0], np.float32), np.array([0, 0, 0], np.float32))
+    img1, T1, k1 = dvr.render(dv, f, to_dev(knots), to_dev(rgba), prm, [c1px])
+    ref1 = oracle.render(vol, of, of["gmax"], sp, knots, rgba, oracle_params(prm), [c1px])
+    _compare_images(img1, T1, k1, ref1, 0.0, "1x1 persp")
+
+
+def _small_diff_scene():
+    w = phantoms.c3(48, 48, views=[0, 3])
+    sub = w.vol[40:88, 40:88, 40:88].copy()
+    w.vol = sub
+    w.cams = [phantoms.ortho_camera(w.dims, w.spacing, 45.0 * k + 5, 20.0, 48, 48) for k in (0, 3)]
+    return w
+
+
+def test_backward_matches_oracle_adjoint():
+    """dL/dTF and dL/dI of L = 1/2 |render - target|^2 (ET off, 16-knot TF) against the oracle's
+    reverse mode, normwise <= 1e-4."""
+    w = _small_diff_scene()
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    tgt_tf = to_dev(w.extra["target_tf_rgba"])
+    target, _, _ = dvr.render(dv, f, kn, tgt_tf, w.params, w.cams, want_state=False)
+    dout = img - target
+    dtf, dvol = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, dout)
+    torch.cuda.synchronize()
+    of = _oracle_feats(dv, w)
+    vol64 = dv.cpu().numpy().astype(np.float64)
+    ref = oracle.render(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba, oracle_params(w.params), w.cams)
+    tref = oracle.render(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, w.extra["target_tf_rgba"],
+                         oracle_params(w.params), w.cams)
+    rtf, rI = oracle.render_vjp(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                                oracle_params(w.params), w.cams, ref["rgba"] - tref["rgba"])
+    e_tf = np.linalg.norm(dtf.cpu().numpy() - rtf) / np.linalg.norm(rtf)
+    e_I = np.linalg.norm(dvol.cpu().numpy() - rI) / np.linalg.norm(rI)
+    print(f"[backward] err dTF={e_tf:.2e} dI={e_I:.2e}", flush=True)
+    assert e_tf <= 1e-4 and e_I <= 1e-4
+
+
+def test_autograd_function():
+    """DVRRender through torch.autograd gives the adjoint's gradients."""
+    w = _small_diff_scene()
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    vol = dv.clone().requires_grad_(True)
+    tf_p = rg.clone().requires_grad_(True)
+    img = dvr.DVRRender.apply(vol, tf_p, f, kn, w.params, w.cams)
+    target = torch.zeros_like(img)
+    loss = 0.5 * ((img - target) ** 2).sum()
+    loss.backward()
+    img2, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    dtf, dvol = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, img2)
+    torch.testing.assert_close(tf_p.grad, dtf, rtol=1e-5, atol=1e-6)
+    torch.testing.assert_close(vol.grad, dvol, rtol=1e-5, atol=1e-7)
+
+
+def test_backward_against_finite_differences():
+    """GPU gradient against FP64 central differences (h = 1e-4) of the oracle's loss on a 32^3
+    crop (features of the crop held fixed): all TF values and up to 96 sampled voxels, <= 1e-3."""
+    w = phantoms.c3(32, 32, views=[0, 5])
+    w.vol = w.vol[48:80, 48:80, 48:80].copy()
+    w.cams = [phantoms.ortho_camera(w.dims, w.spacing, 45.0 * k + 5, 20.0, 32, 32) for k in (0, 5)]
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    rng = np.random.default_rng(9)
+    target = np.clip(img.cpu().numpy() + 0.05 * rng.standard_normal(img.shape), 0, 1)
+    dtf, dvol = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, img - to_dev(target))
+    of = _oracle_feats(dv, w)
+    vol64 = dv.cpu().numpy().astype(np.float64)
+    prm = oracle_params(w.params)
+    tf64 = w.tf_rgba.astype(np.float64)
+
+    def loss(v, tfv):
+        r = oracle.render(v, of, of["gmax"], sp32(w.spacing), w.tf_knots, tfv, prm, w.cams)
+        d = r["rgba"] - target
+        return 0.5 * float(np.sum(d * d))
+
+    h = 1e-4
+    fd = np.zeros_like(tf64)
+    for kk in range(tf64.shape[0]):
+        for ch in range(4):
+            p, m = tf64.copy(), tf64.copy()
+            p[kk, ch] += h
+            m[kk, ch] -= h
+            fd[kk, ch] = (loss(vol64, p) - loss(vol64, m)) / (2 * h)
+    e_tf = np.linalg.norm(dtf.cpu().numpy() - fd) / np.linalg.norm(fd)
+    # a voxel whose +-h perturbation moves some sample across a TF knot sees a kink: its one-sided
+    # differences disagree by far more than the smooth curvature term, and the central difference
+    # is not the derivative there; such voxels are excluded (and counted)
+    idx = [tuple(int(v) for v in rng.integers(4, 28, 3)) for _ in range(96)]
+    L0 = loss(vol64, tf64)
+    fdI, gI, kinks = [], [], 0
+    for ix in idx:
+        p, m = vol64.copy(), vol64.copy()
+        p[ix] += h
+        m[ix] -= h
+        Lp, Lm = loss(p, tf64), loss(m, tf64)
+        dp, dm = (Lp - L0) / h, (L0 - Lm) / h
+        if abs(dp - dm) > 1e-3 * max(abs(dp), abs(dm)) + 1e-9:
+            kinks += 1
+            continue
+        fdI.append((Lp - Lm) / (2 * h))
+        gI.append(float(dvol.cpu().numpy()[ix]))
+    fdI, gI = np.array(fdI), np.array(gI)
+    assert len(fdI) >= 48, f"only {len(fdI)} kink-free voxels"
+    e_I = np.linalg.norm(gI - fdI) / np.linalg.norm(fdI)
+    print(f"[backward-fd] voxels compared {len(fdI)}, straddling a knot {kinks}", flush=True)
+    print(f"[backward-fd] err dTF={e_tf:.2e} dI={e_I:.2e}", flush=True)
+    assert e_tf <= 1e-3 and e_I <= 1e-3
+
+
+def test_normalize_u16_to_f16():
+    """Eq. 1 on uint16 counts to FP16: within one FP16 ulp of the FP64 value rounded to FP16
+    (the FP32 quotient is rounded a second time), and exact at the ends (0 and 1)."""
+    rng = np.random.default_rng(4)
+    raw = rng.integers(300, 61000, (37, 41, 29)).astype(np.uint16)
+    out = dvr.normalize(torch.from_numpy(raw.view(np.int16)).cuda(), torch.float16)
+    ref, mn, mx = oracle.normalize(raw.astype(np.float64))
+    got = out.float().cpu().numpy()
+    r16 = ref.astype(np.float16).astype(np.float64)
+    ulp = np.spacing(np.abs(r16).astype(np.float16)).astype(np.float64)
+    assert np.all(np.abs(got - r16) <= ulp)
+    assert got.min() == 0.0 and got.max() == 1.0
+    out32 = dvr.normalize(torch.from_numpy(raw.view(np.int16)).cuda(), torch.float32)
+    assert rel_err(out32.cpu().numpy(), ref) <= 1e-7
