@@ -45,7 +45,7 @@ __device__ __forceinline__ int64_t to_fix(double q, int n)
     return (int64_t)__double2ll_rn(v);
 }
 
-__device__ __noinline__ RayGeo ray_setup(const KCam &cam, int pi, int pj, const KGrid &g)
+__device__ __forceinline__ RayGeo ray_setup(const KCam cam, int pi, int pj, const KGrid &g)
 {
 #pragma clang fp contract(off)
     RayGeo r;
@@ -201,93 +201,100 @@ __device__ __forceinline__ void corner_setup(const int64_t q[3], uint32_t sx, ui
     c.off[3] = base + sy + sz;
 }
 
-template <int DT>
-__device__ __forceinline__ float interp1(Buf b, const Corners &c, uint32_t sx)
-{
-    float acc = 0.f;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        float v0, v1;
-        if constexpr (DT == DVR_F32) { v0 = ldf(b, c.off[r]); v1 = ldf(b, c.off[r] + 4u); }
-        else { v0 = ldh(b, c.off[r]); v1 = ldh(b, c.off[r] + 2u); }
-        acc = fmaf(c.w[2 * r], v0, acc);
-        acc = fmaf(c.w[2 * r + 1], v1, acc);
-    }
-    (void)sx;
-    return acc;
-}
-
 // Interpolated channels of one sample.
 struct Chan {
     float I, g[3], k, V;
 };
 
-// interleaved F32 record = (I, gx, gy, gz), (k, V, 0, 0); F16 record = 8 halves.
+typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
+
+// Corner values of the current cell, kept across samples: consecutive samples (half a voxel
+// apart) often stay in the same cell, and then no gather is issued for that lane.  Planar
+// layouts load the intensity corners first and the feature corners only for a sample whose
+// extinction is non-zero; an interleaved record brings all six channels in one load per corner
+// (F32: 16 + 8 bytes, F16: 12 bytes kept packed and widened at use).
 template <int LAYOUT, int DT>
-__device__ __forceinline__ void fetch_I(const Vox<LAYOUT, DT> &vx, const Corners &c, Chan &ch, float (&rec)[8][6])
-{
-    if constexpr (LAYOUT == DVR_PLANAR) {
-        ch.I = interp1<DT>(vx.b[0], c, vx.sx);
-        (void)rec;
-    } else {
+struct CornerCache {
+    static constexpr bool kPacked = (LAYOUT == DVR_INTERLEAVED && DT == DVR_F16);
+    uint32_t base;  // byte offset of the cached cell's first corner, or ~0
+    bool feat;      // feature corners valid for this cell
+    float v[kPacked ? 1 : 8][6];
+    uint32_t raw[kPacked ? 8 : 1][3];
+
+    __device__ __forceinline__ void reset()
+    {
+        base = 0xffffffffu;
+        feat = false;
+    }
+
+    __device__ __forceinline__ void need_I(const Vox<LAYOUT, DT> &vx, const Corners &c)
+    {
+        if (c.off[0] == base) return;
+        base = c.off[0];
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
-            // whole-vector casts only: a bit_cast of a single ext-vector element is folded to
-            // element 0 by this compiler at -O3
-            if constexpr (DT == DVR_F32) {
+            if constexpr (LAYOUT == DVR_PLANAR) {
+                if constexpr (DT == DVR_F32) v[e][0] = ldf(vx.b[0], off);
+                else v[e][0] = ldh(vx.b[0], off);
+            } else if constexpr (DT == DVR_F32) {
+                // whole-vector casts only: a bit_cast of a single ext-vector element is folded to
+                // element 0 by this compiler at -O3
                 const f32x4 a = __builtin_bit_cast(f32x4, ld4(vx.b[0], off));
                 const f32x4 b = __builtin_bit_cast(f32x4, ld4(vx.b[0], off + 16u));
-                rec[e][0] = a.x;
-                rec[e][1] = a.y;
-                rec[e][2] = a.z;
-                rec[e][3] = a.w;
-                rec[e][4] = b.x;
-                rec[e][5] = b.y;
+                v[e][0] = a.x;
+                v[e][1] = a.y;
+                v[e][2] = a.z;
+                v[e][3] = a.w;
+                v[e][4] = b.x;
+                v[e][5] = b.y;
             } else {
-                const f16x8 h = __builtin_bit_cast(f16x8, ld4(vx.b[0], off));
-                rec[e][0] = (float)h[0];
-                rec[e][1] = (float)h[1];
-                rec[e][2] = (float)h[2];
-                rec[e][3] = (float)h[3];
-                rec[e][4] = (float)h[4];
-                rec[e][5] = (float)h[5];
+                const u32x4 a = ld4(vx.b[0], off);
+                raw[e][0] = a.x;
+                raw[e][1] = a.y;
+                raw[e][2] = a.z;
             }
         }
+        feat = (LAYOUT == DVR_INTERLEAVED);
+    }
+
+    __device__ __forceinline__ void need_feat(const Vox<LAYOUT, DT> &vx, const Corners &c)
+    {
+        if constexpr (LAYOUT == DVR_PLANAR) {
+            if (feat) return;
+            feat = true;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
+#pragma unroll
+                for (int ch = 1; ch < 6; ++ch) {
+                    if constexpr (DT == DVR_F32) v[e][ch] = ldf(vx.b[ch], off);
+                    else v[e][ch] = ldh(vx.b[ch], off);
+                }
+            }
+        }
+        (void)vx;
+        (void)c;
+    }
+
+    __device__ __forceinline__ float val(int e, int ch) const
+    {
+        if constexpr (kPacked) {
+            const f16x2 h = __builtin_bit_cast(f16x2, raw[e][ch >> 1]);
+            return (float)((ch & 1) ? h.y : h.x);
+        } else {
+            return v[e][ch];
+        }
+    }
+
+    __device__ __forceinline__ float interp(const Corners &c, int ch) const
+    {
         float acc = 0.f;
 #pragma unroll
-        for (int e = 0; e < 8; ++e) acc = fmaf(c.w[e], rec[e][0], acc);
-        ch.I = acc;
+        for (int e = 0; e < 8; ++e) acc = fmaf(c.w[e], val(e, ch), acc);
+        return acc;
     }
-}
-
-template <int LAYOUT, int DT>
-__device__ __forceinline__ void fetch_rest(const Vox<LAYOUT, DT> &vx, const Corners &c, Chan &ch, const float (&rec)[8][6])
-{
-    if constexpr (LAYOUT == DVR_PLANAR) {
-        ch.g[0] = interp1<DT>(vx.b[1], c, vx.sx);
-        ch.g[1] = interp1<DT>(vx.b[2], c, vx.sx);
-        ch.g[2] = interp1<DT>(vx.b[3], c, vx.sx);
-        ch.k = interp1<DT>(vx.b[4], c, vx.sx);
-        ch.V = interp1<DT>(vx.b[5], c, vx.sx);
-        (void)rec;
-    } else {
-        float a1 = 0.f, a2 = 0.f, a3 = 0.f, a4 = 0.f, a5 = 0.f;
-#pragma unroll
-        for (int e = 0; e < 8; ++e) {
-            a1 = fmaf(c.w[e], rec[e][1], a1);
-            a2 = fmaf(c.w[e], rec[e][2], a2);
-            a3 = fmaf(c.w[e], rec[e][3], a3);
-            a4 = fmaf(c.w[e], rec[e][4], a4);
-            a5 = fmaf(c.w[e], rec[e][5], a5);
-        }
-        ch.g[0] = a1;
-        ch.g[1] = a2;
-        ch.g[2] = a3;
-        ch.k = a4;
-        ch.V = a5;
-    }
-}
+};
 
 // Optical state of one sample.
 struct Opt {
@@ -329,6 +336,24 @@ __device__ __forceinline__ void eq4(const KRender &rp, float invg, const Chan &c
 }
 
 // ------------------------------------------------------------------------------------------------
+// The camera index is uniform over the workgroup; copying the record field by field keeps the
+// by-value kernel argument block in the constant segment (taking its address would make the
+// compiler copy the whole block to per-lane scratch).
+__device__ __forceinline__ KCam load_cam(const KLaunch &L, uint32_t cam)
+{
+    cam = __builtin_amdgcn_readfirstlane(cam);
+    KCam c;
+    c.persp = L.cams[cam].persp;
+#pragma unroll
+    for (int a = 0; a < 3; ++a) {
+        c.o[a] = L.cams[cam].o[a];
+        c.d0[a] = L.cams[cam].d0[a];
+        c.du[a] = L.cams[cam].du[a];
+        c.dv[a] = L.cams[cam].dv[a];
+    }
+    return c;
+}
+
 __device__ __forceinline__ void pixel_of(const KLaunch &L, uint32_t &cam, int &pi, int &pj, bool &valid)
 {
     // XCD-aware order: consecutive dispatch slots go to different XCDs, so logical tile t is placed
@@ -362,7 +387,7 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
     const float invg = gm > 0.f ? 1.f / gm : 0.f;
     RayGeo r;
     r.N = 0;
-    if (valid) r = ray_setup(L.cams[cam], pi, pj, g);
+    if (valid) r = ray_setup(load_cam(L, cam), pi, pj, g);
     const size_t pix = valid ? ((size_t)(L.cam_base + cam) * L.H + pj) * L.W + pi : 0;
     float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f, Tprev = 1.f;
     int last = -1, shaded = 0;
@@ -372,18 +397,25 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
         int64_t q[3] = {r.q0[0], r.q0[1], r.q0[2]};
         int64_t dq[3] = {r.dq[0], r.dq[1], r.dq[2]};
         float dk = (r.N == 1) ? r.dlast : r.delta;
+        CornerCache<LAYOUT, DT> cc;
+        cc.reset();
         for (int k = 0; k < r.N; ++k) {
             Corners c;
             corner_setup(q, vx.sx, vx.sy, vx.sz, c);
             Chan ch;
-            float rec[8][6];
-            fetch_I<LAYOUT, DT>(vx, c, ch, rec);
+            cc.need_I(vx, c);
+            ch.I = cc.interp(c, 0);
             Opt o;
             tf_eval<KMAX>(sh, kx, ch.I, o);
             Tprev = T;
             if (o.tau > 0.f) {
                 ++shaded;
-                fetch_rest<LAYOUT, DT>(vx, c, ch, rec);
+                cc.need_feat(vx, c);
+                ch.g[0] = cc.interp(c, 1);
+                ch.g[1] = cc.interp(c, 2);
+                ch.g[2] = cc.interp(c, 3);
+                ch.k = cc.interp(c, 4);
+                ch.V = cc.interp(c, 5);
                 eq4(rp, invg, ch, dk, o);
                 const float ta = T * o.alpha;
                 C0 = fmaf(ta, o.c[0], C0);
@@ -471,7 +503,7 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
     if (kl >= 0) {
         const float gm = *feat.gmax;
         const float invg = gm > 0.f ? 1.f / gm : 0.f;
-        const RayGeo r = ray_setup(L.cams[cam], pi, pj, g);
+        const RayGeo r = ray_setup(load_cam(L, cam), pi, pj, g);
         const float4 gr = reinterpret_cast<const float4 *>(L.dout)[pix];
         const float gC0 = gr.x, gC1 = gr.y, gC2 = gr.z, gA = gr.w;
         float T = L.T_last[pix];
@@ -486,17 +518,24 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
         SegAcc sa;
         sa.seg = -2;
         for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;
+        CornerCache<LAYOUT, DT> cc;
+        cc.reset();
         for (int k = kl; k >= 0; --k) {
             const float dk = (k == r.N - 1) ? r.dlast : r.delta;
             Corners c;
             corner_setup(q, vx.sx, vx.sy, vx.sz, c);
             Chan ch;
-            float rec[8][6];
-            fetch_I<LAYOUT, DT>(vx, c, ch, rec);
+            cc.need_I(vx, c);
+            ch.I = cc.interp(c, 0);
             Opt o;
             tf_eval<KMAX>(sh, kx, ch.I, o);
             if (o.tau > 0.f) {
-                fetch_rest<LAYOUT, DT>(vx, c, ch, rec);
+                cc.need_feat(vx, c);
+                ch.g[0] = cc.interp(c, 1);
+                ch.g[1] = cc.interp(c, 2);
+                ch.g[2] = cc.interp(c, 3);
+                ch.k = cc.interp(c, 4);
+                ch.V = cc.interp(c, 5);
                 eq4(rp, invg, ch, dk, o);
             } else {
                 o.alpha = 0.f;
