@@ -529,19 +529,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
             ch.I = cc.interp(c, 0);
             Opt o;
             tf_eval<KMAX>(sh, kx, ch.I, o);
-            if (o.tau > 0.f) {
-                cc.need_feat(vx, c);
-                ch.g[0] = cc.interp(c, 1);
-                ch.g[1] = cc.interp(c, 2);
-                ch.g[2] = cc.interp(c, 3);
-                ch.k = cc.interp(c, 4);
-                ch.V = cc.interp(c, 5);
-                eq4(rp, invg, ch, dk, o);
-            } else {
-                o.alpha = 0.f;
-                o.om = 1.f;
-                o.M = 0.f;
-            }
+            // unlike the forward pass, a sample with zero extinction is not skipped: its alpha is 0,
+            // but dalpha/dtau = (1 - alpha) M delta is not, so the TF-value gradient needs M
+            cc.need_feat(vx, c);
+            ch.g[0] = cc.interp(c, 1);
+            ch.g[1] = cc.interp(c, 2);
+            ch.g[2] = cc.interp(c, 3);
+            ch.k = cc.interp(c, 4);
+            ch.V = cc.interp(c, 5);
+            eq4(rp, invg, ch, dk, o);
             if (k < kl) T = T / o.om;
             const float Ta = T * o.alpha;
             const float dal = T * (gC0 * (o.c[0] - S0) + gC1 * (o.c[1] - S1) + gC2 * (o.c[2] - S2) + gA * R);

@@ -40,6 +40,8 @@ C1_SEMI_MM = ((28.0, 25.0, 22.0), (24.0, 21.0, 18.0), (17.0, 14.0, 12.0))
 # Head phantom: shells as fractions of the half-extent, outermost first, with values.
 HEAD_SHELLS = ((0.95, 0.9), (0.88, 0.05), (0.82, 0.2), (0.76, 0.55), (0.55, 0.8))
 HEAD_HALF_MM = (90.0, 108.0, 90.0)
+# Vessel tubes are painted out to TUBE_CUT radii, where the Gaussian profile is below 1e-6 of its peak.
+TUBE_CUT = 5.3
 
 
 @dataclass
@@ -111,10 +113,34 @@ def _paint_slab(out, z_mm, x_mm, y_mm, shells, centre, tubes, ventricles=()):
         q = ((X - cen[0]) / semi[0]) ** 2 + ((Y - cen[1]) / semi[1]) ** 2 + ((Z - cen[2]) / semi[2]) ** 2
         out[np.broadcast_to(q <= 1.0, out.shape)] = val
     for p0, u, r_mm, peak in tubes:
-        dx, dy, dz = X - p0[0], Y - p0[1], Z - p0[2]
+        # the profile is below 1e-6 of its peak beyond TUBE_CUT * R: paint only the part of the slab
+        # within that distance of the line (bounding box of the line's passage through the slab)
+        reach = TUBE_CUT * r_mm
+        zlo, zhi = z_mm[0] - reach, z_mm[-1] + reach
+        if abs(u[2]) > 1e-9:
+            ta, tb = (zlo - p0[2]) / u[2], (zhi - p0[2]) / u[2]
+            t0, t1 = min(ta, tb), max(ta, tb)
+            xs = (p0[0] + t0 * u[0], p0[0] + t1 * u[0])
+            ys = (p0[1] + t0 * u[1], p0[1] + t1 * u[1])
+            bx = (min(xs) - reach, max(xs) + reach)
+            by = (min(ys) - reach, max(ys) + reach)
+        else:
+            if p0[2] < zlo or p0[2] > zhi:
+                continue
+            bx = (-np.inf, np.inf)
+            by = (-np.inf, np.inf)
+        ix = np.nonzero((x_mm >= bx[0]) & (x_mm <= bx[1]))[0]
+        iy = np.nonzero((y_mm >= by[0]) & (y_mm <= by[1]))[0]
+        if len(ix) == 0 or len(iy) == 0:
+            continue
+        sx, sy = slice(ix[0], ix[-1] + 1), slice(iy[0], iy[-1] + 1)
+        dx, dy, dz = X[..., sx] - p0[0], Y[:, sy, :] - p0[1], Z - p0[2]
         along = dx * u[0] + dy * u[1] + dz * u[2]
         d2 = dx * dx + dy * dy + dz * dz - along * along
-        np.maximum(out, peak * np.exp(-np.maximum(d2, 0.0) / (2.0 * r_mm * r_mm)), out=out)
+        prof = peak * np.exp(-np.maximum(d2, 0.0) / (2.0 * r_mm * r_mm))
+        prof[d2 > reach * reach] = 0.0
+        sub = out[:, sy, sx]
+        np.maximum(sub, prof, out=sub)
 
 
 def _draw_tubes(rng, n, r_lo, r_hi, centre, half, h_min):

@@ -197,6 +197,35 @@ def test_backward_matches_oracle_adjoint():
     assert e_tf <= 1e-4 and e_I <= 1e-4
 
 
+def test_backward_transparent_band_and_et():
+    """Adjoint with a TF whose first knots have zero extinction (transparent band) and early
+    termination: the TF-value gradient of the transparent band is not zero (making it slightly
+    opaque changes the image), so transparent samples must still be differentiated."""
+    w = phantoms.c2(64, 64, views=[10, 100])
+    w.vol = w.vol[30:110, 40:140, 40:130].copy()
+    w.cams = [phantoms.persp_camera(w.dims, w.spacing, 10.0 + 90 * k, 15.0, 64, 64) for k in range(2)]
+    dv, f = _gpu_scene(w)
+    kn, rg = tf_dev(w)
+    assert w.tf_rgba[0, 3] == 0.0 and w.tf_rgba[1, 3] == 0.0
+    tgt = phantoms.perturb_tf(np.random.default_rng(3), w.tf_rgba)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    target, _, _ = dvr.render(dv, f, kn, to_dev(tgt), w.params, w.cams, want_state=False)
+    dtf, dvol = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, img - target)
+    torch.cuda.synchronize()
+    of = _oracle_feats(dv, w)
+    vol64 = dv.cpu().numpy().astype(np.float64)
+    prm = oracle_params(w.params)
+    ref = oracle.render(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba, prm, w.cams)
+    tref = oracle.render(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, tgt, prm, w.cams)
+    rtf, rI = oracle.render_vjp(vol64, of, of["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba, prm, w.cams,
+                                ref["rgba"] - tref["rgba"])
+    assert abs(rtf[0, 3]) > 1e-3 * np.abs(rtf).max()
+    e_tf = np.linalg.norm(dtf.cpu().numpy() - rtf) / np.linalg.norm(rtf)
+    e_I = np.linalg.norm(dvol.cpu().numpy() - rI) / np.linalg.norm(rI)
+    print(f"[backward] transparent band + ET: err dTF={e_tf:.2e} dI={e_I:.2e}", flush=True)
+    assert e_tf <= 1e-4 and e_I <= 1e-4
+
+
 def test_autograd_function():
     """DVRRender through torch.autograd gives the adjoint's gradients."""
     w = _small_diff_scene()
