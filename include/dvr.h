@@ -170,6 +170,67 @@ dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_gri
                                const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
                                const float *dL_drgba, float *dL_dtf, float *dL_dvol, hipStream_t stream);
 
+/* ---------------------------------------------------------------------------------------------
+ * Batched launch: the feature pass of many volumes (uneven shapes, anisotropic spacing) and the
+ * raymarch of many views of them, in one persistent kernel recorded in a HIP graph.  The kernel
+ * drains a queue of work items in a fixed order (z-filter slabs, then feature tiles, then ray
+ * tiles); a feature tile waits for its volume's z-filter items and a ray tile for its volume's
+ * feature items (per-volume completion counters, release/acquire at device scope).  Because items
+ * are taken in queue order and an item only waits for items taken before it, every awaited item
+ * is held by a running workgroup and the launch cannot deadlock; each wait is still bounded and
+ * reports DVR_E_TIMEOUT through dvr_batch_check instead of hanging.
+ * The transfer function is read from device memory at every launch: editing it needs no new plan
+ * (the analogue of the paper's uniform buffers, Sec. 4). */
+
+typedef struct dvr_batch_volume {
+    const void *vol;        /* device [nz][ny][nx] of vol_dtype (DVR_F32 or DVR_F16) */
+    int32_t vol_dtype;
+    dvr_grid grid;
+    dvr_features_buf feat;  /* device feature buffers written by each launch (all volumes share dtype and layout) */
+} dvr_batch_volume;
+
+typedef struct dvr_batch_view {
+    int32_t volume;         /* index into the volume array */
+    dvr_camera cam;         /* each view has its own image size */
+    float *rgba;            /* device [H][W][4] */
+    float *T_last;          /* device [H][W], nullable */
+    int32_t *k_last;        /* device [H][W], nullable (written only if T_last is given) */
+} dvr_batch_view;
+
+/* Tile and brick shapes of a batched launch (chosen by dvr_batch_autotune or given). */
+typedef struct dvr_tune {
+    int32_t wg_per_cu; /* persistent workgroups per compute unit, 1..8 */
+    int32_t xy_tile;   /* feature tile (x by y voxels): 0 = 64x8, 1 = 32x16, 2 = 128x4 */
+    int32_t xy_zrun;   /* z slices per feature item, 1..32 */
+    int32_t z_chunk;   /* z slices per z-filter item, 1..64 */
+    int32_t ray_tile;  /* rays per wave within a 16x16 workgroup tile: 0 = 8x8, 1 = 16x4, 2 = 4x16 */
+} dvr_tune;
+
+typedef struct dvr_batch_desc {
+    int32_t nvol;
+    const dvr_batch_volume *vols;  /* host array */
+    int32_t nview;
+    const dvr_batch_view *views;   /* host array */
+    dvr_feature_params fp;         /* shared by all volumes; c must be > 0 */
+    dvr_tf tf;                     /* shared; device memory */
+    dvr_render_params rp;          /* shared */
+    const dvr_tune *tune;          /* nullable: defaults */
+} dvr_batch_desc;
+
+typedef struct dvr_batch dvr_batch; /* opaque plan: owns its work tables, workspace, counters and graph */
+
+/* Builds the plan (validates, allocates, uploads the tables, records the graph).  Synchronous. */
+dvr_status dvr_batch_create(const dvr_batch_desc *desc, dvr_batch **plan);
+/* Enqueues one replay of the plan's graph on stream.  Asynchronous. */
+dvr_status dvr_batch_launch(dvr_batch *plan, hipStream_t stream);
+/* Waits for stream and reports DVR_E_TIMEOUT if a dependency wait of the last launch expired. */
+dvr_status dvr_batch_check(dvr_batch *plan, hipStream_t stream);
+dvr_status dvr_batch_destroy(dvr_batch *plan);
+/* Picks the tile shapes: times each candidate dvr_tune on this batch (graph replays, HIP events)
+ * and returns the fastest.  With cache_path, results are kept in a JSON file keyed by the batch's
+ * shape class and reused.  Synchronous; overwrites the batch's outputs. */
+dvr_status dvr_batch_autotune(const dvr_batch_desc *desc, const char *cache_path, dvr_tune *best);
+
 #ifdef __cplusplus
 }
 #endif

@@ -17,7 +17,7 @@ from . import _abi as abi
 from ._abi import DVRError
 
 __all__ = ["Features", "features", "render", "render_backward", "normalize", "DVRRender", "DVRError",
-           "camera_struct", "lib"]
+           "camera_struct", "lib", "Batch"]
 
 
 def lib():
@@ -228,3 +228,73 @@ class DVRRender(torch.autograd.Function):
                                     k_last, dimg, want_dvol=ctx.needs_input_grad[0])
         return (dvol if ctx.needs_input_grad[0] else None, dtf if ctx.needs_input_grad[1] else None,
                 None, None, None, None)
+
+
+class Batch:
+    """A batched plan (dvr_batch_*): the feature pass of every volume and the raymarch of every view
+    in one persistent kernel recorded in a HIP graph.
+
+    vols: list of device volumes [nz][ny][nx]; spacings: list of (hx, hy, hz); feats: list of
+    Features (outputs, one per volume, same dtype and layout); views: list of
+    (volume index, camera, rgba [H][W][4] tensor, T_last or None, k_last or None).
+    The TF tensors are read at every launch: edit them in place to change the transfer function."""
+
+    def __init__(self, vols, spacings, feats, views, sigmas, knots, rgba, params, alpha=0.5, beta=0.5, c=0.1,
+                 eig_gap=1e-2, tune=None):
+        self._keep = (list(vols), list(feats), list(views), knots, rgba)
+        self.desc = self._desc(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha, beta, c, eig_gap, tune)
+        self.plan = C.c_void_p()
+        abi.check(lib().dvr_batch_create(C.byref(self.desc), C.byref(self.plan)))
+
+    def _desc(self, vols, spacings, feats, views, sigmas, knots, rgba, params, alpha, beta, c, eig_gap, tune):
+        self._va = (abi.BatchVolume * len(vols))()
+        for i, (v, sp, f) in enumerate(zip(vols, spacings, feats)):
+            _require_cuda(v)
+            self._va[i] = abi.BatchVolume(v.data_ptr(), _dt(v), grid_struct(v.shape, sp), f.buf())
+        self._wa = (abi.BatchView * max(len(views), 1))()
+        for i, (vi, cam, img, T, k) in enumerate(views):
+            _require_cuda(img)
+            self._wa[i] = abi.BatchView(int(vi), cam if isinstance(cam, abi.Camera) else camera_struct(cam),
+                                        img.data_ptr(), T.data_ptr() if T is not None else None,
+                                        k.data_ptr() if k is not None else None)
+        self._tune = None
+        if tune is not None:
+            self._tune = tune if isinstance(tune, abi.Tune) else abi.Tune(*[int(tune[k]) for k in TUNE_FIELDS])
+        d = abi.BatchDesc()
+        d.nvol, d.vols = len(vols), self._va
+        d.nview, d.views = len(views), self._wa
+        d.fp = _fparams(sigmas, alpha, beta, c, eig_gap)
+        d.tf = _tf_struct(knots, rgba)
+        d.rp = _rparams(params)
+        d.tune = C.pointer(self._tune) if self._tune is not None else None
+        return d
+
+    def launch(self):
+        abi.check(lib().dvr_batch_launch(self.plan, _stream()))
+
+    def check(self):
+        abi.check(lib().dvr_batch_check(self.plan, _stream()))
+
+    def close(self):
+        if self.plan:
+            lib().dvr_batch_destroy(self.plan)
+            self.plan = C.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def autotune(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2,
+                 cache_path=None):
+        """dvr_batch_autotune: returns the fastest tune as a dict (and caches it in cache_path)."""
+        tmp = Batch.__new__(Batch)
+        d = tmp._desc(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha, beta, c, eig_gap, None)
+        t = abi.Tune()
+        abi.check(lib().dvr_batch_autotune(C.byref(d), cache_path.encode() if cache_path else None, C.byref(t)))
+        return {k: getattr(t, k) for k in TUNE_FIELDS}
+
+
+TUNE_FIELDS = ("wg_per_cu", "xy_tile", "xy_zrun", "z_chunk", "ray_tile")

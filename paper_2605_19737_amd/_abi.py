@@ -53,6 +53,26 @@ class RayState(C.Structure):
     _fields_ = [("T_last", C.c_void_p), ("k_last", C.c_void_p), ("counters", C.c_void_p)]
 
 
+class BatchVolume(C.Structure):
+    _fields_ = [("vol", C.c_void_p), ("vol_dtype", C.c_int32), ("grid", Grid), ("feat", FeaturesBuf)]
+
+
+class BatchView(C.Structure):
+    _fields_ = [("volume", C.c_int32), ("cam", Camera), ("rgba", C.c_void_p), ("T_last", C.c_void_p),
+                ("k_last", C.c_void_p)]
+
+
+class Tune(C.Structure):
+    _fields_ = [("wg_per_cu", C.c_int32), ("xy_tile", C.c_int32), ("xy_zrun", C.c_int32), ("z_chunk", C.c_int32),
+                ("ray_tile", C.c_int32)]
+
+
+class BatchDesc(C.Structure):
+    _fields_ = [("nvol", C.c_int32), ("vols", C.POINTER(BatchVolume)), ("nview", C.c_int32),
+                ("views", C.POINTER(BatchView)), ("fp", FeatureParams), ("tf", TF), ("rp", RenderParams),
+                ("tune", C.POINTER(Tune))]
+
+
 class DVRError(RuntimeError):
     def __init__(self, status, msg):
         super().__init__(f"{STATUS.get(status, status)}: {msg}")
@@ -82,8 +102,14 @@ def load():
                              P(RayState), vp]
     L.dvr_render_backward.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32,
                                       P(RayState), vp, vp, vp, vp]
+    L.dvr_batch_create.argtypes = [P(BatchDesc), P(vp)]
+    L.dvr_batch_launch.argtypes = [vp, vp]
+    L.dvr_batch_check.argtypes = [vp, vp]
+    L.dvr_batch_destroy.argtypes = [vp]
+    L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
     for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_features",
-                 "dvr_render", "dvr_render_backward"):
+                 "dvr_render", "dvr_render_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
+                 "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32
     _lib = L
     return L

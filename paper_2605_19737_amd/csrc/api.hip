@@ -11,11 +11,13 @@
 #include "common.hpp"
 #include "render_args.hpp"
 
+#include "host.hpp"
+
 namespace dvr {
 hipError_t launch_fill_zero(float *p, int64_t n, hipStream_t st);
 }
 
-namespace {
+namespace dvr::host {
 
 thread_local std::string g_err;
 
@@ -124,7 +126,9 @@ void axis_taps(double sigma_vox, double h, dvr::AxisTaps &t)
 
 size_t features_ws_bytes(const dvr_grid *g) { return 256 + (size_t)12 * (size_t)nvox(g); }
 
-}  // namespace
+}  // namespace dvr::host
+
+using namespace dvr::host;
 
 extern "C" {
 
@@ -198,7 +202,9 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
     return DVR_OK;
 }
 
-static dvr_status build_render_args(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+}  // extern "C"
+
+dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
                                     const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
                                     const dvr_camera *cams, int32_t ncam, dvr::RenderArgs &a, dvr::KCam *kc)
 {
@@ -275,6 +281,8 @@ static dvr_status build_render_args(const void *vol, int32_t vol_dtype, const dv
     a.ncam = ncam;
     return DVR_OK;
 }
+
+extern "C" {
 
 dvr_status dvr_render(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_features_buf *feat,
                       const dvr_tf *tf, const dvr_render_params *rp, const dvr_camera *cams, int32_t ncam,

@@ -164,3 +164,35 @@ def test_binding_fails_loudly_without_library(tmp_path, monkeypatch):
     monkeypatch.setattr(abi, "_lib", None)
     with pytest.raises(ImportError):
         abi.load()
+
+
+def _bdesc(nvol=1, c=0.1, tune=None, view_vol=0):
+    vols = (abi.BatchVolume * nvol)()
+    for i in range(nvol):
+        vols[i] = abi.BatchVolume(FAKE, abi.DVR_F32, _grid(), _fb())
+    views = (abi.BatchView * 1)(abi.BatchView(view_vol, _cam(), FAKE, None, None))
+    d = abi.BatchDesc()
+    d.nvol, d.vols, d.nview, d.views = nvol, vols, 1, views
+    d.fp = _fp(c=c)
+    d.tf = abi.TF(4, FAKE, FAKE)
+    d.rp = _rp()
+    d.tune = C.pointer(tune) if tune is not None else None
+    return d, (vols, views, tune)
+
+
+@pytest.mark.parametrize("kind,code", [("c", -4), ("tune", -1), ("view", -1), ("novol", -1)])
+def test_batch_create_rejects(L, kind, code):
+    """Batched plans validate everything before allocating or launching anything."""
+    if kind == "c":
+        d, keep = _bdesc(c=0.0)
+    elif kind == "tune":
+        d, keep = _bdesc(tune=abi.Tune(0, 0, 4, 8, 0))
+    elif kind == "view":
+        d, keep = _bdesc(view_vol=3)
+    else:
+        d, keep = _bdesc()
+        d.nvol = 0
+    plan = C.c_void_p()
+    s, msg = _status(L, "dvr_batch_create", C.byref(d), C.byref(plan))
+    assert s == code and msg and not plan.value
+    assert L.dvr_batch_destroy(None) == 0

@@ -1,0 +1,135 @@
+"""Batched persistent launch (dvr_batch_*): the features of several uneven, anisotropic volumes and
+4 views of each, in one persistent kernel recorded in a HIP graph.  Every volume's features and
+every view's image and ray state equal the standalone dvr_features / dvr_render results bitwise
+(the same arithmetic per voxel and per ray), for every tile shape the autotuner can choose; a TF
+edited in place is picked up by the next replay; the dependency-wait timeout path reports
+DVR_E_TIMEOUT while the kernel still exits normally."""
+import os
+
+import numpy as np
+import pytest
+import torch
+
+import paper_2605_19737_amd as dvr
+import phantoms
+from paper_2605_19737_amd import _abi as abi
+from tests.gpu_common import to_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def _scene(nvol=5, res=96, layout=abi.DVR_PLANAR, dtype=torch.float32, sigmas=(1.0,)):
+    ws = [phantoms.c4_volume(b, res, res) for b in range(nvol)]
+    vols = [to_dev(w.vol, dtype) for w in ws]
+    spacings = [w.spacing for w in ws]
+    feats = [dvr.alloc_features(tuple(v.shape), sp, dtype, layout) for v, sp in zip(vols, spacings)]
+    views = []
+    for i, w in enumerate(ws):
+        for cam in w.cams:
+            img = torch.empty((cam.height, cam.width, 4), dtype=torch.float32, device="cuda")
+            T = torch.empty((cam.height, cam.width), dtype=torch.float32, device="cuda")
+            k = torch.empty((cam.height, cam.width), dtype=torch.int32, device="cuda")
+            views.append((i, cam, img, T, k))
+    knots, rgba = to_dev(ws[0].tf_knots), to_dev(ws[0].tf_rgba)
+    return ws, vols, spacings, feats, views, knots, rgba, list(sigmas)
+
+
+def _standalone(ws, vols, spacings, views, knots, rgba, sigmas, layout, dtype):
+    out_f, out_v = [], []
+    for w, v, sp in zip(ws, vols, spacings):
+        out_f.append(dvr.features(v, sp, sigmas, c=w.c, dtype=dtype, layout=layout))
+    for (i, cam, _, _, _) in views:
+        vv = vols[i] if layout == abi.DVR_PLANAR else None
+        out_v.append(dvr.render(vv, out_f[i], knots, rgba, ws[i].params, [cam]))
+    return out_f, out_v
+
+
+def _assert_equal(feats, views, ref_f, ref_v):
+    for a, b in zip(feats, ref_f):
+        assert torch.equal(a.grad, b.grad)
+        if a.kappa is not None:
+            assert torch.equal(a.kappa, b.kappa) and torch.equal(a.ves, b.ves)
+        assert torch.equal(a.gmax, b.gmax)
+    for (i, cam, img, T, k), (rimg, rT, rk) in zip(views, ref_v):
+        assert torch.equal(img, rimg[0]) and torch.equal(T, rT[0]) and torch.equal(k, rk[0])
+
+
+@pytest.mark.parametrize("tune", [None, dict(wg_per_cu=2, xy_tile=1, xy_zrun=3, z_chunk=5, ray_tile=1),
+                                  dict(wg_per_cu=8, xy_tile=2, xy_zrun=1, z_chunk=64, ray_tile=2)])
+def test_batch_equals_standalone(tune):
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene()
+    print(f"[batch] {len(vols)} volumes {[tuple(v.shape) for v in vols]}, {len(views)} views, tune {tune}", flush=True)
+    b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c, tune=tune)
+    b.launch()
+    b.check()
+    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, abi.DVR_PLANAR, torch.float32)
+    torch.cuda.synchronize()
+    _assert_equal(feats, views, ref_f, ref_v)
+    # replay twice more: counters and |g|_max are reset by the graph itself
+    b.launch()
+    b.launch()
+    b.check()
+    _assert_equal(feats, views, ref_f, ref_v)
+    b.close()
+
+
+def test_batch_multiscale_fp16_interleaved():
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=3, layout=abi.DVR_INTERLEAVED,
+                                                                dtype=torch.float16, sigmas=(1.0, 2.0))
+    b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c)
+    b.launch()
+    b.check()
+    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, abi.DVR_INTERLEAVED, torch.float16)
+    torch.cuda.synchronize()
+    _assert_equal(feats, views, ref_f, ref_v)
+    b.close()
+
+
+def test_batch_tf_update_without_new_plan():
+    """The TF is read from device memory at each replay (the paper's uniform-buffer interaction)."""
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=2)
+    b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c)
+    b.launch()
+    b.check()
+    rgba.copy_(to_dev(phantoms.perturb_tf(np.random.default_rng(2), ws[0].tf_rgba)))
+    b.launch()
+    b.check()
+    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, abi.DVR_PLANAR, torch.float32)
+    torch.cuda.synchronize()
+    _assert_equal(feats, views, ref_f, ref_v)
+    b.close()
+
+
+def test_batch_autotune_and_cache(tmp_path):
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=3, res=64)
+    cache = str(tmp_path / "tune.json")
+    t = dvr.Batch.autotune(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c, cache_path=cache)
+    print(f"[batch] autotuned {t}", flush=True)
+    assert os.path.exists(cache) and open(cache).read().count("[") == 1
+    t2 = dvr.Batch.autotune(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c, cache_path=cache)
+    assert t2 == t
+    b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c, tune=t)
+    b.launch()
+    b.check()
+    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, abi.DVR_PLANAR, torch.float32)
+    torch.cuda.synchronize()
+    _assert_equal(feats, views, ref_f, ref_v)
+    b.close()
+
+
+def test_batch_timeout_reported(monkeypatch):
+    """Host-forced condition: the rays of volume 0 wait for one feature item more than exist, with a
+    short bound; the launch finishes and dvr_batch_check reports DVR_E_TIMEOUT."""
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=2, res=32)
+    monkeypatch.setenv("DVR_BATCH_TEST_TIMEOUT", "1")
+    b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c)
+    monkeypatch.delenv("DVR_BATCH_TEST_TIMEOUT")
+    b.launch()
+    with pytest.raises(dvr.DVRError) as e:
+        b.check()
+    assert e.value.status == -8
+    b.close()
+    b2 = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c)
+    b2.launch()
+    b2.check()
+    b2.close()
