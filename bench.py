@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 # Algorithmic flops per raymarch sample (FMA = 2); see the design notes for the breakdown.
 FLOP_SHADED = 144
 FLOP_TRANSPARENT = 40
-RENDER_SOURCES = ["render.hip", "render_args.hpp", "common.hpp"]
+RENDER_SOURCES = ["render.hip", "render_dev.hpp", "render_args.hpp", "common.hpp"]
 
 
 def log(msg):
@@ -68,6 +68,10 @@ def main():
     ap.add_argument("--views", type=int, default=360, help="views per step (the workload has 360)")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-backward-leg", action="store_true")
+    ap.add_argument("--no-fp16-leg", action="store_true")
+    ap.add_argument("--no-batch-leg", action="store_true")
+    ap.add_argument("--no-c5-leg", action="store_true")
+    ap.add_argument("--only-main", action="store_true", help="just the timed head-phantom steps (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -163,6 +167,15 @@ def main():
              "rays_per_step": V * 1024 * 1024}
 
     # ------------------------------------------------------------------ fwd+bwd ms/view leg
+    if args.only_main:
+        args.no_backward_leg = args.no_fp16_leg = args.no_batch_leg = args.no_c5_leg = True
+        args.no_cpu_baseline = True
+    if not args.no_fp16_leg:
+        comps["fp16_records"] = leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log)
+    if not args.no_batch_leg:
+        comps["batched"] = leg_batch(dev, stream, dvr, torch, np, log)
+    if not args.no_c5_leg:
+        comps["c5_fp16_fwd_bwd"] = leg_c5(dev, stream, dvr, torch, np, log)
     if not args.no_backward_leg:
         log("differentiable-render leg: 128^3, 8 views at 512^2, forward + adjoint")
         w3 = phantoms.c3(512, 512)
@@ -233,6 +246,144 @@ def main():
                       "voxels": nvox, "views": V, "image": [1024, 1024]},
            "roofline": roofline, "cpu_baseline": cpu, "components": comps}
     print(json.dumps(out), flush=True)
+
+
+def leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log):
+    """Same head workload with FP16 volume and FP16 interleaved feature records (FP32 arithmetic)."""
+    from paper_2605_19737_amd import _abi as abi
+    log("FP16-record leg: same step with an FP16 volume and FP16 feature records")
+    v16 = vol.half()
+    f16 = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float16, abi.DVR_INTERLEAVED)
+    ws = torch.empty(dvr.features_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c), dtype=torch.uint8,
+                     device=vol.device)
+    img = torch.empty((len(cams), 1024, 1024, 4), dtype=torch.float32, device=vol.device)
+    cnt = torch.zeros(2, dtype=torch.int64, device=vol.device)
+    ev = []
+    for it in range(K + 1):
+        a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        a.record(stream)
+        dvr.features(v16, w.spacing, w.sigmas, c=w.c, dtype=torch.float16, layout=abi.DVR_INTERLEAVED, out=f16, ws=ws)
+        b.record(stream)
+        dvr.render(None, f16, knots, tf, w.params, cams, out=img, counters=cnt)
+        c.record(stream)
+        if it > 0:
+            ev.append((a, b, c))
+    torch.cuda.synchronize()
+    tf_ = sum(a.elapsed_time(b) for a, b, _ in ev) / 1e3
+    tr = sum(b.elapsed_time(c) for _, b, c in ev) / 1e3
+    evaluated = int(cnt[0].item())
+    out = {"samples_per_s": evaluated * K / (tf_ + tr), "render_samples_per_s": evaluated * K / tr,
+           "render_ms_per_view": 1e3 * tr / (K * len(cams)), "features_ms": 1e3 * tf_ / K,
+           "image_error_bound": "compute 1e-5 of range given the stored FP16 values; storage 2^-11 per feature; "
+                                "end to end 5.4e-4 max / 1.2e-5 mean measured at 512x512x400"}
+    log(f"FP16 records: {out['samples_per_s']:.4g} samples/s over the step ({out['render_ms_per_view']:.3f} ms/view)")
+    return out
+
+
+def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
+    """64 uneven anisotropic volumes, features + 4 views each at 512^2, in one persistent graph launch
+    (autotuned), against the same work as per-call launches."""
+    import phantoms
+    log(f"batched leg: building {nvol} volumes")
+    ws = [phantoms.c4_volume(b, 512, 512) for b in range(nvol)]
+    vols = [torch.from_numpy(w.vol).to(dev) for w in ws]
+    sps = [w.spacing for w in ws]
+    feats = [dvr.alloc_features(tuple(v.shape), sp) for v, sp in zip(vols, sps)]
+    views = []
+    for i, w in enumerate(ws):
+        for cam in w.cams:
+            views.append((i, dvr.camera_struct(cam), torch.empty((512, 512, 4), dtype=torch.float32, device=dev),
+                          None, None))
+    knots = torch.from_numpy(ws[0].tf_knots).to(dev)
+    tf = torch.from_numpy(ws[0].tf_rgba).to(dev)
+    nvox = sum(v.numel() for v in vols)
+    log("batched leg: autotuning")
+    tune = dvr.Batch.autotune(vols, sps, feats, views, ws[0].sigmas, knots, tf, ws[0].params, c=ws[0].c,
+                              cache_path=os.path.join("/tmp", "dvr_tune_cache.json"))
+    b = dvr.Batch(vols, sps, feats, views, ws[0].sigmas, knots, tf, ws[0].params, c=ws[0].c, tune=tune)
+    b.launch()
+    b.check()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    reps = 3
+    e0.record(stream)
+    for _ in range(reps):
+        b.launch()
+    e1.record(stream)
+    b.check()
+    t_batch = e0.elapsed_time(e1) / 1e3 / reps
+    b.close()
+    # the same work as per-call launches (features per volume, then 4 views per volume), with counters
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+    total = 0
+    pf = [dvr.alloc_features(tuple(v.shape), sp) for v, sp in zip(vols, sps)]
+    wsp = [torch.empty(dvr.features_workspace_bytes(tuple(v.shape), sp, ws[0].sigmas, c=ws[0].c), dtype=torch.uint8,
+                       device=dev) for v, sp in zip(vols, sps)]
+    imgs = [torch.empty((4, 512, 512, 4), dtype=torch.float32, device=dev) for _ in vols]
+
+    def per_call(count):
+        nonlocal total
+        for i, (w, v, sp) in enumerate(zip(ws, vols, sps)):
+            dvr.features(v, sp, w.sigmas, c=w.c, out=pf[i], ws=wsp[i])
+            dvr.render(v, pf[i], knots, tf, w.params, [dvr.camera_struct(c) for c in w.cams], out=imgs[i],
+                       counters=cnt if count else None)
+            if count:
+                torch.cuda.synchronize()
+                total += int(cnt[0].item())
+
+    per_call(True)
+    e0.record(stream)
+    per_call(False)
+    e1.record(stream)
+    torch.cuda.synchronize()
+    t_calls = e0.elapsed_time(e1) / 1e3
+    out = {"volumes": nvol, "voxels": nvox, "views": len(views), "image": [512, 512], "tune": tune,
+           "graph_launch_ms": 1e3 * t_batch, "samples_evaluated": total, "samples_per_s": total / t_batch,
+           "per_call_ms": 1e3 * t_calls, "per_call_samples_per_s": total / t_calls}
+    log(f"batched: {1e3 * t_batch:.2f} ms per graph launch ({total / t_batch:.4g} samples/s) vs per-call "
+        f"{1e3 * t_calls:.2f} ms ({total / t_calls:.4g} samples/s); tune {tune}")
+    return out
+
+
+def leg_c5(dev, stream, dvr, torch, np, log):
+    """512x512x400 uint16 -> Eq. 1 -> FP16 records -> 8 views at 2048^2, forward + adjoint."""
+    import phantoms
+    from paper_2605_19737_amd import _abi as abi
+    log("FP16 scale leg: 512x512x400 uint16, 8 views at 2048^2, forward + adjoint")
+    w = phantoms.c5(2048, 2048)
+    raw = torch.from_numpy(w.vol.view(np.int16)).to(dev)
+    knots = torch.from_numpy(w.tf_knots).to(dev)
+    tf = torch.from_numpy(w.tf_rgba).to(dev)
+    tgt = torch.from_numpy(w.extra["target_tf_rgba"]).to(dev)
+    cams = [dvr.camera_struct(c) for c in w.cams]
+    f = dvr.alloc_features(tuple(raw.shape), w.spacing, torch.float16, abi.DVR_INTERLEAVED)
+    wsf = torch.empty(dvr.features_workspace_bytes(tuple(raw.shape), w.spacing, w.sigmas, c=w.c),
+                      dtype=torch.uint8, device=dev)
+    cnt = torch.zeros(2, dtype=torch.int64, device=dev)
+    times = []
+    for it in range(3):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(5)]
+        ev[0].record(stream)
+        v16 = dvr.normalize(raw, torch.float16)
+        ev[1].record(stream)
+        dvr.features(v16, w.spacing, w.sigmas, c=w.c, eig_gap=1e-3, dtype=torch.float16, layout=abi.DVR_INTERLEAVED,
+                     out=f, ws=wsf)
+        ev[2].record(stream)
+        img, T, k = dvr.render(None, f, knots, tf, w.params, cams, counters=cnt)
+        ev[3].record(stream)
+        if it == 0:
+            target, _, _ = dvr.render(None, f, knots, tgt, w.params, cams, want_state=False)
+        dvr.render_backward(None, f, knots, tf, w.params, cams, T, k, img - target)
+        ev[4].record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(4)])
+    t = np.median(np.array(times), axis=0)
+    evaluated = int(cnt[0].item())
+    out = {"normalize_ms": float(t[0]), "features_ms": float(t[1]), "fwd_ms_per_view": float(t[2]) / 8,
+           "bwd_ms_per_view": float(t[3]) / 8, "fwd_bwd_ms_per_view": float(t[2] + t[3]) / 8,
+           "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3)}
+    log(f"C5: normalize {t[0]:.2f} ms, features {t[1]:.2f} ms, fwd {t[2] / 8:.2f} ms/view, bwd {t[3] / 8:.2f} ms/view")
+    return out
 
 
 if __name__ == "__main__":
