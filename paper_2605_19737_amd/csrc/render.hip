@@ -95,9 +95,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
 {
     __shared__ TFShared<KMAX> sh;
     __shared__ float tfa[KMAX * 4];
+    __shared__ float win[4][kWin];  // one dL/dI accumulation window per wave
     float kx[KMAX];
     tf_load<KMAX>(sh, kx, tf);
     for (int p = threadIdx.x; p < KMAX * 4; p += 256) tfa[p] = 0.f;
+    float *wwin = win[threadIdx.x >> 6];
+    if (L.dvol)
+        for (int p = threadIdx.x & 63; p < kWin; p += 64) wwin[p] = 0.f;
     __syncthreads();
     const int K = tf.K;
     uint32_t cam;
@@ -106,13 +110,19 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
     pixel_of(L, cam, pi, pj, valid);
     const size_t pix = valid ? ((size_t)(L.cam_base + cam) * L.H + pj) * L.W + pi : 0;
     const int kl = valid ? L.k_last[pix] : -1;
+    const float gm = *feat.gmax;
+    const float invg = gm > 0.f ? 1.f / gm : 0.f;
+    RayGeo r;
+    r.N = 0;
+    float4 gr = make_float4(0.f, 0.f, 0.f, 0.f);
+    float Tl = 0.f;
     if (kl >= 0) {
-        const float gm = *feat.gmax;
-        const float invg = gm > 0.f ? 1.f / gm : 0.f;
-        const RayGeo r = ray_setup(load_cam(L, cam), pi, pj, g);
-        const float4 gr = reinterpret_cast<const float4 *>(L.dout)[pix];
-        march_bwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r, kl, L.T_last[pix], gr, K, tfa, L.dvol);
+        r = ray_setup(load_cam(L, cam), pi, pj, g);
+        gr = reinterpret_cast<const float4 *>(L.dout)[pix];
+        Tl = L.T_last[pix];
     }
+    // every lane of the wave takes part (the dL/dI window is managed wave-wide)
+    march_bwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r, kl, Tl, gr, K, tfa, L.dvol, wwin);
     __syncthreads();
     for (int p = threadIdx.x; p < K * 4; p += 256)
         if (tfa[p] != 0.f) atomicAdd(L.dtf + p, tfa[p]);

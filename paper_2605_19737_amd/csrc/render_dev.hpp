@@ -395,16 +395,7 @@ __device__ __forceinline__ void count_samples(unsigned long long *counters, int 
 }
 
 // ------------------------------------------------------------------------------------------------
-// Adjoint (back to front from the stored (T_last, k_last)).  With suffix colour S and suffix
-// transmittance R of the samples behind k:
-//   dL/dalpha_k = T_k (gC . (c_k - S) + gA R),   dL/dc_k = gC T_k alpha_k,
-//   S <- alpha_k c_k + (1 - alpha_k) S,  R <- (1 - alpha_k) R,  T_{k-1} = T_k / (1 - alpha_{k-1}),
-// then alpha = 1 - exp(-tau M delta_k) gives dL/dtau = dL/dalpha (1 - alpha) M delta_k; the TF is
-// linear in its knot values on the sample's segment, and dL/dI_sample = sum_ch dL/dv_ch slope_ch is
-// scattered to the 8 corners with the trilinear weights.
-// TF-gradient accumulation: a lane adds into registers while its ray stays on one TF segment and
-// flushes to a workgroup array in LDS (LDS atomics) when the segment changes; the workgroup array
-// is added to the global [K][4] gradient with one atomic per parameter at the end.
+// Adjoint helpers.  TF-gradient accumulator of one lane: the register sums of the current TF segment.
 struct SegAcc {
     int seg;         // current key: -1 below the first knot, 0..K-2 inside, K-1 above the last
     float lo[4], hi[4];
@@ -425,31 +416,124 @@ struct SegAcc {
     }
 };
 
+// dL/dI scatter.  Neighbouring rays of a wave put their samples' corner weights on the same few
+// voxels in the same instruction, and global float atomics on one address serialize in L2, so
+// each wave first accumulates into its own window of kWX x kWY x kWZ voxels in LDS and adds the
+// window to dL/dI (one atomic per touched voxel) when a lane's cell falls outside it.  The window
+// is re-placed around the cells of the lanes that need it, reaching ahead in the direction the
+// rays walk (back to front); a lane whose corners do not fit adds to global memory directly.
+constexpr int kWX = 16, kWY = 16, kWZ = 8, kWin = kWX * kWY * kWZ;
+
+__device__ __forceinline__ int wave_min_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = min(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+__device__ __forceinline__ int wave_max_i(int v)
+{
+    for (int o = 32; o > 0; o >>= 1) v = max(v, __shfl_xor(v, o, 64));
+    return v;
+}
+
+struct DWin {
+    float *w;   // this wave's kWin floats in LDS, index (z * kWY + y) * kWX + x
+    int o[3];   // voxel index of entry (0, 0, 0); wave-uniform
+    bool live;  // window placed (it may hold partial sums)
+
+    // add every non-zero entry to dvol and clear it (all lanes of the wave)
+    __device__ __forceinline__ void flush(float *dvol, const KGrid &g)
+    {
+        const int lane = threadIdx.x & 63;
+#pragma unroll 4
+        for (int j = 0; j < kWin / 64; ++j) {
+            const int e = lane + 64 * j;
+            const float v = w[e];
+            if (v != 0.f) {
+                const int ex = e % kWX, ey = (e / kWX) % kWY, ez = e / (kWX * kWY);
+                const uint32_t gi = ((uint32_t)(o[2] + ez) * (uint32_t)g.n[1] + (uint32_t)(o[1] + ey)) *
+                                        (uint32_t)g.n[0] + (uint32_t)(o[0] + ex);
+                atomicAdd(dvol + gi, v);
+                w[e] = 0.f;
+            }
+        }
+    }
+
+    __device__ __forceinline__ bool holds(const int cc[3]) const
+    {
+        return (uint32_t)(cc[0] - o[0]) <= (uint32_t)(kWX - 2) && (uint32_t)(cc[1] - o[1]) <= (uint32_t)(kWY - 2) &&
+               (uint32_t)(cc[2] - o[2]) <= (uint32_t)(kWZ - 2);
+    }
+
+    // new origin from the cells of the lanes with need set (all lanes of the wave); dq_lead is the
+    // front-to-back step of one of those lanes
+    __device__ __forceinline__ void place(bool need, const int cc[3], const int64_t dq_lead[3])
+    {
+        const int W[3] = {kWX, kWY, kWZ};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            const int lo = wave_min_i(need ? cc[a] : 0x7fffffff);
+            const int hi = wave_max_i(need ? cc[a] : -0x7fffffff);
+            // back to front the cells move against dq: put the window's slack on that side
+            const int oa = dq_lead[a] > 0 ? hi + 2 - W[a] : lo;
+            o[a] = __builtin_amdgcn_readfirstlane(oa);
+        }
+        live = true;
+    }
+};
+
+// Adjoint (back to front from the stored (T_last, k_last)).  With suffix colour S and suffix
+// transmittance R of the samples behind k:
+//   dL/dalpha_k = T_k (gC . (c_k - S) + gA R),   dL/dc_k = gC T_k alpha_k,
+//   S <- alpha_k c_k + (1 - alpha_k) S,  R <- (1 - alpha_k) R,  T_{k-1} = T_k / (1 - alpha_{k-1}),
+// then alpha = 1 - exp(-tau M delta_k) gives dL/dtau = dL/dalpha (1 - alpha) M delta_k; the TF is
+// linear in its knot values on the sample's segment, and dL/dI_sample = sum_ch dL/dv_ch slope_ch is
+// scattered to the 8 corners with the trilinear weights.
+// TF-gradient accumulation: a lane adds into registers while its ray stays on one TF segment and
+// flushes to a workgroup array in LDS (LDS atomics) when the segment changes; the workgroup array
+// is added to the global [K][4] gradient with one atomic per parameter at the end.
+//
+// Every lane of the wave calls this (kl = -1 for a lane without a ray).  The loop runs over the
+// sample index k from the wave's largest k_last down to 0, a lane taking part once k <= its own
+// k_last, so at each step the lanes sit at the same sample index (the same depth for rays that
+// entered through the same face) and the loop control stays wave-uniform for the dL/dI window.
 template <int LAYOUT, int DT, int KMAX>
 __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, const TFShared<KMAX> &sh,
                                           const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r,
-                                          int kl, float T_last, float4 gr, int K, float *tfa, float *dvol)
+                                          int kl, float T_last, float4 gr, int K, float *tfa, float *dvol,
+                                          float *win /* this wave's kWin floats of LDS, zeroed */)
 {
     const float gC0 = gr.x, gC1 = gr.y, gC2 = gr.z, gA = gr.w;
-    {
-        float T = T_last;
-        float S0 = 0.f, S1 = 0.f, S2 = 0.f, R = 1.f;
-        Vox<LAYOUT, DT> vx;
-        vx.init(feat, g);
-        int64_t q[3];
-        const bool at_last = (kl == r.N - 1);
-        for (int a = 0; a < 3; ++a) q[a] = at_last ? r.ql[a] : r.q0[a] + (int64_t)kl * r.dq[a];
-        // byte offset of a corner -> voxel index (element sizes are powers of two)
-        const uint32_t esh = (LAYOUT == DVR_PLANAR) ? (DT == DVR_F32 ? 2u : 1u) : (DT == DVR_F32 ? 5u : 4u);
-        SegAcc sa;
-        sa.seg = -2;
-        for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;
-        CornerCache<LAYOUT, DT> cc;
-        cc.reset();
-        for (int k = kl; k >= 0; --k) {
+    float T = T_last;
+    float S0 = 0.f, S1 = 0.f, S2 = 0.f, R = 1.f;
+    Vox<LAYOUT, DT> vx;
+    vx.init(feat, g);
+    int64_t q[3];
+    const bool at_last = (kl == r.N - 1);
+    for (int a = 0; a < 3; ++a) q[a] = (kl < 0) ? 0 : (at_last ? r.ql[a] : r.q0[a] + (int64_t)kl * r.dq[a]);
+    // byte offset of a corner -> voxel index (element sizes are powers of two)
+    const uint32_t esh = (LAYOUT == DVR_PLANAR) ? (DT == DVR_F32 ? 2u : 1u) : (DT == DVR_F32 ? 5u : 4u);
+    SegAcc sa;
+    sa.seg = -2;
+    for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;
+    CornerCache<LAYOUT, DT> cc;
+    cc.reset();
+    DWin dw;
+    dw.w = win;
+    dw.live = false;
+    dw.o[0] = dw.o[1] = dw.o[2] = 0;
+    const int kmax = __builtin_amdgcn_readfirstlane(wave_max_i(kl));
+    for (int k = kmax; k >= 0; --k) {
+        const bool act = (k <= kl);
+        float Ib = 0.f;
+        Corners c;
+        int cell[3] = {0, 0, 0};
+        if (act) {
             const float dk = (k == r.N - 1) ? r.dlast : r.delta;
-            Corners c;
             corner_setup(q, vx.sx, vx.sy, vx.sz, c);
+            cell[0] = (int)(q[0] >> 32);
+            cell[1] = (int)(q[1] >> 32);
+            cell[2] = (int)(q[2] >> 32);
             Chan ch;
             cc.need_I(vx, c);
             ch.I = cc.interp(c, 0);
@@ -491,27 +575,47 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                     sa.lo[e] = fmaf(1.f - t, vb[e], sa.lo[e]);
                     sa.hi[e] = fmaf(t, vb[e], sa.hi[e]);
                 }
-                if (dvol) {
-                    const float4 s = sh.s[key];
-                    const float Ib = vb[0] * s.x + vb[1] * s.y + vb[2] * s.z + vb[3] * s.w;
-                    if (Ib != 0.f) {
-#pragma unroll
-                        for (int e = 0; e < 8; ++e) {
-                            const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
-                            atomicAdd(dvol + (off >> esh), c.w[e] * Ib);
-                        }
-                    }
-                }
-            }
-            if (k > 0) {
-                const bool from_last = (k == r.N - 1) && r.N >= 2;
-                q[0] -= from_last ? r.dql[0] : r.dq[0];
-                q[1] -= from_last ? r.dql[1] : r.dq[1];
-                q[2] -= from_last ? r.dql[2] : r.dq[2];
+                const float4 s = sh.s[key];
+                Ib = vb[0] * s.x + vb[1] * s.y + vb[2] * s.z + vb[3] * s.w;
             }
         }
-        if (sa.seg != -2) sa.flush(tfa, K);
+        if (dvol) {
+            const bool need = act && Ib != 0.f;
+            bool in = need && dw.live && dw.holds(cell);
+            const uint64_t miss = __ballot(need && !in);
+            if (miss) {
+                const int lead = __ffsll((unsigned long long)miss) - 1;
+                int64_t dql[3];
+                for (int a = 0; a < 3; ++a) dql[a] = __shfl(r.dq[a], lead, 64);
+                if (dw.live) dw.flush(dvol, g);
+                dw.place(need, cell, dql);
+                in = need && dw.holds(cell);
+            }
+            if (in) {
+                const int b = ((cell[2] - dw.o[2]) * kWY + (cell[1] - dw.o[1])) * kWX + (cell[0] - dw.o[0]);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const int d = ((e >> 2) & 1) * kWX * kWY + ((e >> 1) & 1) * kWX + (e & 1);
+                    // wave scope: only this wave touches its window
+                    __hip_atomic_fetch_add(win + b + d, c.w[e] * Ib, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            } else if (need) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
+                    atomicAdd(dvol + (off >> esh), c.w[e] * Ib);
+                }
+            }
+        }
+        if (act && k > 0) {
+            const bool from_last = (k == r.N - 1) && r.N >= 2;
+            q[0] -= from_last ? r.dql[0] : r.dq[0];
+            q[1] -= from_last ? r.dql[1] : r.dq[1];
+            q[2] -= from_last ? r.dql[2] : r.dq[2];
+        }
     }
+    if (dvol && dw.live) dw.flush(dvol, g);
+    if (sa.seg != -2) sa.flush(tfa, K);
 }
 
 }  // namespace dvr
