@@ -46,6 +46,9 @@ __device__ __forceinline__ KCam load_cam(const KLaunch &L, uint32_t cam)
     return c;
 }
 
+// MORTON: the 64 lanes of a wave take their 8 x 8 pixels in Morton order (lane bits x0 y0 x1 y1 x2
+// y2), so each quad of lanes is a 2 x 2 pixel block; otherwise row-major.
+template <bool MORTON = false>
 __device__ __forceinline__ void pixel_of(const KLaunch &L, uint32_t &cam, int &pi, int &pj, bool &valid)
 {
     // XCD-aware order: consecutive dispatch slots go to different XCDs, so logical tile t is placed
@@ -59,8 +62,16 @@ __device__ __forceinline__ void pixel_of(const KLaunch &L, uint32_t &cam, int &p
     const uint32_t tt = t - cam * tpv;
     const uint32_t ty = tt / tiles_x, tx = tt - ty * tiles_x;
     const uint32_t lane = threadIdx.x & 63u, wv = threadIdx.x >> 6;
-    pi = (int)(tx * 16u + (wv & 1u) * 8u + (lane & 7u));
-    pj = (int)(ty * 16u + (wv >> 1) * 8u + (lane >> 3));
+    uint32_t lx, ly;
+    if (MORTON) {
+        lx = (lane & 1u) | ((lane >> 1) & 2u) | ((lane >> 2) & 4u);
+        ly = ((lane >> 1) & 1u) | ((lane >> 2) & 2u) | ((lane >> 3) & 4u);
+    } else {
+        lx = lane & 7u;
+        ly = lane >> 3;
+    }
+    pi = (int)(tx * 16u + (wv & 1u) * 8u + lx);
+    pj = (int)(ty * 16u + (wv >> 1) * 8u + ly);
     valid = cam < (uint32_t)L.ncam && pi < L.W && pj < L.H;
 }
 
@@ -94,20 +105,21 @@ template <int LAYOUT, int DT, int KMAX>
 __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf, KRender rp, KLaunch L)
 {
     __shared__ TFShared<KMAX> sh;
-    __shared__ float tfa[KMAX * 4];
-    __shared__ float win[4][kWin];  // one dL/dI accumulation window per wave
+    constexpr int kCopies = tf_copies(KMAX);
+    __shared__ double tfa[KMAX * 4 * kCopies];
+    __shared__ double win[4][kWin];  // one dL/dI accumulation window per wave
     float kx[KMAX];
     tf_load<KMAX>(sh, kx, tf);
-    for (int p = threadIdx.x; p < KMAX * 4; p += 256) tfa[p] = 0.f;
-    float *wwin = win[threadIdx.x >> 6];
+    for (int p = threadIdx.x; p < KMAX * 4 * kCopies; p += 256) tfa[p] = 0.0;
+    double *wwin = win[threadIdx.x >> 6];
     if (L.dvol)
-        for (int p = threadIdx.x & 63; p < kWin; p += 64) wwin[p] = 0.f;
+        for (int p = threadIdx.x & 63; p < kWin; p += 64) wwin[p] = 0.0;
     __syncthreads();
     const int K = tf.K;
     uint32_t cam;
     int pi, pj;
     bool valid;
-    pixel_of(L, cam, pi, pj, valid);
+    pixel_of<true>(L, cam, pi, pj, valid);
     const size_t pix = valid ? ((size_t)(L.cam_base + cam) * L.H + pj) * L.W + pi : 0;
     const int kl = valid ? L.k_last[pix] : -1;
     const float gm = *feat.gmax;
@@ -122,10 +134,15 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
         Tl = L.T_last[pix];
     }
     // every lane of the wave takes part (the dL/dI window is managed wave-wide)
-    march_bwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r, kl, Tl, gr, K, tfa, L.dvol, wwin);
+    march_bwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r, kl, Tl, gr, K, tfa + (threadIdx.x % kCopies), L.dvol,
+                                wwin);
     __syncthreads();
-    for (int p = threadIdx.x; p < K * 4; p += 256)
-        if (tfa[p] != 0.f) atomicAdd(L.dtf + p, tfa[p]);
+    for (int p = threadIdx.x; p < K * 4; p += 256) {
+        double acc = 0.0;
+#pragma unroll
+        for (int j = 0; j < kCopies; ++j) acc += tfa[p * kCopies + j];
+        if (acc != 0.0) atomicAdd(L.dtf + p, (float)acc);
+    }
 }
 
 // ------------------------------------------------------------------------------------------------

@@ -396,20 +396,33 @@ __device__ __forceinline__ void count_samples(unsigned long long *counters, int 
 
 // ------------------------------------------------------------------------------------------------
 // Adjoint helpers.  TF-gradient accumulator of one lane: the register sums of the current TF segment.
+// The workgroup's TF-gradient array is FP64 (see the dL/dI window on LDS atomics) and kept in
+// tf_copies(KMAX) interleaved copies (entry p of copy j at p * copies + j, lane l using copy
+// l % copies), so lanes of a wave that flush the same knot in the same instruction mostly add to
+// different LDS words.
+__host__ __device__ constexpr int tf_copies(int kmax) { return kmax <= 8 ? 16 : (kmax <= 16 ? 8 : 1); }
+
+template <int COPIES>
 struct SegAcc {
     int seg;         // current key: -1 below the first knot, 0..K-2 inside, K-1 above the last
     float lo[4], hi[4];
 
-    __device__ __forceinline__ void flush(float *tfa, int K)
+    __device__ __forceinline__ static void add(double *p, float v)
+    {
+        __hip_atomic_fetch_add(p, (double)v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP);
+    }
+
+    // tfa: this lane's copy (workgroup array + lane % COPIES)
+    __device__ __forceinline__ void flush(double *tfa, int K)
     {
         if (seg < 0 || seg >= K - 1) {
             const int kn = seg < 0 ? 0 : K - 1;
             for (int e = 0; e < 4; ++e)
-                if (lo[e] != 0.f) atomicAdd(tfa + kn * 4 + e, lo[e]);
+                if (lo[e] != 0.f) add(tfa + (kn * 4 + e) * COPIES, lo[e]);
         } else {
             for (int e = 0; e < 4; ++e) {
-                if (lo[e] != 0.f) atomicAdd(tfa + seg * 4 + e, lo[e]);
-                if (hi[e] != 0.f) atomicAdd(tfa + (seg + 1) * 4 + e, hi[e]);
+                if (lo[e] != 0.f) add(tfa + (seg * 4 + e) * COPIES, lo[e]);
+                if (hi[e] != 0.f) add(tfa + ((seg + 1) * 4 + e) * COPIES, hi[e]);
             }
         }
         for (int e = 0; e < 4; ++e) lo[e] = hi[e] = 0.f;
@@ -417,12 +430,16 @@ struct SegAcc {
 };
 
 // dL/dI scatter.  Neighbouring rays of a wave put their samples' corner weights on the same few
-// voxels in the same instruction, and global float atomics on one address serialize in L2, so
-// each wave first accumulates into its own window of kWX x kWY x kWZ voxels in LDS and adds the
-// window to dL/dI (one atomic per touched voxel) when a lane's cell falls outside it.  The window
-// is re-placed around the cells of the lanes that need it, reaching ahead in the direction the
-// rays walk (back to front); a lane whose corners do not fit adds to global memory directly.
-constexpr int kWX = 16, kWY = 16, kWZ = 8, kWin = kWX * kWY * kWZ;
+// voxels in the same instruction, and global float atomics on one address serialize, so each wave
+// first accumulates into its own window of voxels in LDS and adds the window to dL/dI (one atomic
+// per touched voxel) when a lane's cell falls outside it.  The window is re-placed around the cells
+// of the lanes that need it, reaching ahead in the direction the rays walk (back to front); a lane
+// whose corners do not fit adds to global memory directly.
+// The window is kWin0 x kWin1 x kWin2 entries, its longest side along the volume axis the rays
+// advance on fastest and its shortest along the slowest (fixed per wave at its first placement).
+// Entries are FP64: LDS atomic adds on FP64 run at about the rate of integer ones on this chip,
+// while FP32 LDS atomic adds are many times slower.
+constexpr int kWin0 = 16, kWin1 = 12, kWin2 = 8, kWin = kWin0 * kWin1 * kWin2;
 
 __device__ __forceinline__ int wave_min_i(int v)
 {
@@ -436,46 +453,105 @@ __device__ __forceinline__ int wave_max_i(int v)
     return v;
 }
 
+// Pairwise merge inside each quad of lanes (xor 1, then xor 2): where both lanes of a pair hold the
+// same key, the lower lane adds the upper lane's values and the upper lane drops out.  Keys must be
+// unique for lanes without values.  All lanes of the wave must be active.
+template <int CTRL, int BIT>
+__device__ __forceinline__ void quad_merge_step(bool &has, int key, float (&v)[8])
+{
+    const int pk = __builtin_amdgcn_update_dpp(0, key, CTRL, 0xF, 0xF, false);
+    const int ph = __builtin_amdgcn_update_dpp(0, has ? 1 : 0, CTRL, 0xF, 0xF, false);
+    const bool same = (pk == key);
+    const bool upper = ((threadIdx.x >> BIT) & 1u) != 0u;
+#pragma unroll
+    for (int e = 0; e < 8; ++e) {
+        const float pv =
+            __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[e]), CTRL, 0xF, 0xF, false));
+        v[e] = same ? (upper ? 0.f : v[e] + pv) : v[e];
+    }
+    has = same ? (!upper && (has || ph != 0)) : has;
+}
+
+__device__ __forceinline__ void quad_merge(bool &has, int key, float (&v)[8])
+{
+    quad_merge_step<0xB1, 0>(has, key, v);  // quad_perm [1,0,3,2]: partner lane ^ 1
+    quad_merge_step<0x4E, 1>(has, key, v);  // quad_perm [2,3,0,1]: partner lane ^ 2
+}
+
 struct DWin {
-    float *w;   // this wave's kWin floats in LDS, index (z * kWY + y) * kWX + x
-    int o[3];   // voxel index of entry (0, 0, 0); wave-uniform
-    bool live;  // window placed (it may hold partial sums)
+    double *w;    // this wave's kWin entries in LDS, index u0 + kWin0 (u1 + kWin1 u2)
+    int o[3];     // voxel index (x, y, z) of the window's first entry; wave-uniform
+    int ext[3];   // window extent along voxel axis x, y, z
+    int st[3];    // window index stride of voxel axis x, y, z
+    int gst[3];   // dL/dI index stride of the voxel axis on window rank 0, 1, 2
+    int crn[8];   // window index offsets of the 8 cell corners (bit 0 x, bit 1 y, bit 2 z)
+    bool live;    // window placed (it may hold partial sums)
+
+    // ranks of the voxel axes by |dq| (descending), from one lane's front-to-back step
+    __device__ __forceinline__ void orient(const int64_t dq[3], const KGrid &g)
+    {
+        const int64_t ax = dq[0] < 0 ? -dq[0] : dq[0], ay = dq[1] < 0 ? -dq[1] : dq[1], az = dq[2] < 0 ? -dq[2] : dq[2];
+        int r[3];  // rank of axis x, y, z
+        r[0] = (ay > ax) + (az > ax);
+        r[1] = (ax >= ay) + (az > ay);
+        r[2] = (ax >= az) + (ay >= az);
+        const int W[3] = {kWin0, kWin1, kWin2};
+        const int S[3] = {1, kWin0, kWin0 * kWin1};
+        const int G[3] = {1, g.n[0], g.n[0] * g.n[1]};
+#pragma unroll
+        for (int a = 0; a < 3; ++a) {
+            ext[a] = __builtin_amdgcn_readfirstlane(W[r[a]]);
+            st[a] = __builtin_amdgcn_readfirstlane(S[r[a]]);
+        }
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const int a = (r[0] == k) ? 0 : ((r[1] == k) ? 1 : 2);
+            gst[k] = __builtin_amdgcn_readfirstlane(G[a]);
+        }
+#pragma unroll
+        for (int e = 0; e < 8; ++e) crn[e] = (e & 1) * st[0] + ((e >> 1) & 1) * st[1] + ((e >> 2) & 1) * st[2];
+    }
 
     // add every non-zero entry to dvol and clear it (all lanes of the wave)
     __device__ __forceinline__ void flush(float *dvol, const KGrid &g)
     {
         const int lane = threadIdx.x & 63;
+        const int olin = o[0] + o[1] * g.n[0] + o[2] * g.n[0] * g.n[1];
 #pragma unroll 4
         for (int j = 0; j < kWin / 64; ++j) {
             const int e = lane + 64 * j;
-            const float v = w[e];
-            if (v != 0.f) {
-                const int ex = e % kWX, ey = (e / kWX) % kWY, ez = e / (kWX * kWY);
-                const uint32_t gi = ((uint32_t)(o[2] + ez) * (uint32_t)g.n[1] + (uint32_t)(o[1] + ey)) *
-                                        (uint32_t)g.n[0] + (uint32_t)(o[0] + ex);
-                atomicAdd(dvol + gi, v);
-                w[e] = 0.f;
+            const double v = w[e];
+            if (v != 0.0) {
+                const int u0 = e % kWin0, u1 = (e / kWin0) % kWin1, u2 = e / (kWin0 * kWin1);
+                // entries are only ever written for in-bounds voxels, so gi is in [0, N)
+                const int gi = olin + u0 * gst[0] + u1 * gst[1] + u2 * gst[2];
+                atomicAdd(dvol + gi, (float)v);
+                w[e] = 0.0;
             }
         }
     }
 
     __device__ __forceinline__ bool holds(const int cc[3]) const
     {
-        return (uint32_t)(cc[0] - o[0]) <= (uint32_t)(kWX - 2) && (uint32_t)(cc[1] - o[1]) <= (uint32_t)(kWY - 2) &&
-               (uint32_t)(cc[2] - o[2]) <= (uint32_t)(kWZ - 2);
+        return (uint32_t)(cc[0] - o[0]) <= (uint32_t)(ext[0] - 2) && (uint32_t)(cc[1] - o[1]) <= (uint32_t)(ext[1] - 2) &&
+               (uint32_t)(cc[2] - o[2]) <= (uint32_t)(ext[2] - 2);
+    }
+
+    __device__ __forceinline__ int index(const int cc[3]) const
+    {
+        return (cc[0] - o[0]) * st[0] + (cc[1] - o[1]) * st[1] + (cc[2] - o[2]) * st[2];
     }
 
     // new origin from the cells of the lanes with need set (all lanes of the wave); dq_lead is the
     // front-to-back step of one of those lanes
     __device__ __forceinline__ void place(bool need, const int cc[3], const int64_t dq_lead[3])
     {
-        const int W[3] = {kWX, kWY, kWZ};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
             const int lo = wave_min_i(need ? cc[a] : 0x7fffffff);
             const int hi = wave_max_i(need ? cc[a] : -0x7fffffff);
             // back to front the cells move against dq: put the window's slack on that side
-            const int oa = dq_lead[a] > 0 ? hi + 2 - W[a] : lo;
+            const int oa = dq_lead[a] > 0 ? hi + 2 - ext[a] : lo;
             o[a] = __builtin_amdgcn_readfirstlane(oa);
         }
         live = true;
@@ -500,8 +576,8 @@ struct DWin {
 template <int LAYOUT, int DT, int KMAX>
 __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, const TFShared<KMAX> &sh,
                                           const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r,
-                                          int kl, float T_last, float4 gr, int K, float *tfa, float *dvol,
-                                          float *win /* this wave's kWin floats of LDS, zeroed */)
+                                          int kl, float T_last, float4 gr, int K, double *tfa, float *dvol,
+                                          double *win /* this wave's kWin entries of LDS, zeroed */)
 {
     const float gC0 = gr.x, gC1 = gr.y, gC2 = gr.z, gA = gr.w;
     float T = T_last;
@@ -513,7 +589,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
     for (int a = 0; a < 3; ++a) q[a] = (kl < 0) ? 0 : (at_last ? r.ql[a] : r.q0[a] + (int64_t)kl * r.dq[a]);
     // byte offset of a corner -> voxel index (element sizes are powers of two)
     const uint32_t esh = (LAYOUT == DVR_PLANAR) ? (DT == DVR_F32 ? 2u : 1u) : (DT == DVR_F32 ? 5u : 4u);
-    SegAcc sa;
+    SegAcc<tf_copies(KMAX)> sa;
     sa.seg = -2;
     for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;
     CornerCache<LAYOUT, DT> cc;
@@ -521,6 +597,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
     DWin dw;
     dw.w = win;
     dw.live = false;
+    bool oriented = false;
     dw.o[0] = dw.o[1] = dw.o[2] = 0;
     const int kmax = __builtin_amdgcn_readfirstlane(wave_max_i(kl));
     for (int k = kmax; k >= 0; --k) {
@@ -580,7 +657,14 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
             }
         }
         if (dvol) {
-            const bool need = act && Ib != 0.f;
+            bool need = act && Ib != 0.f;
+            float cw[8];
+#pragma unroll
+            for (int e = 0; e < 8; ++e) cw[e] = need ? c.w[e] * Ib : 0.f;
+            // LDS atomics on one address from several lanes of an instruction are serialized; the
+            // lanes of a quad (2 x 2 pixels) that sit in the same cell merge their corner values
+            // first (the lower lane of each pair takes the sum).
+            quad_merge(need, need ? (int)(c.off[0] >> esh) : (int)(0x80000000u | threadIdx.x), cw);
             bool in = need && dw.live && dw.holds(cell);
             const uint64_t miss = __ballot(need && !in);
             if (miss) {
@@ -588,22 +672,26 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 int64_t dql[3];
                 for (int a = 0; a < 3; ++a) dql[a] = __shfl(r.dq[a], lead, 64);
                 if (dw.live) dw.flush(dvol, g);
+                if (!oriented) {
+                    dw.orient(dql, g);
+                    oriented = true;
+                }
                 dw.place(need, cell, dql);
                 in = need && dw.holds(cell);
             }
             if (in) {
-                const int b = ((cell[2] - dw.o[2]) * kWY + (cell[1] - dw.o[1])) * kWX + (cell[0] - dw.o[0]);
+                const int b = dw.index(cell);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    const int d = ((e >> 2) & 1) * kWX * kWY + ((e >> 1) & 1) * kWX + (e & 1);
                     // wave scope: only this wave touches its window
-                    __hip_atomic_fetch_add(win + b + d, c.w[e] * Ib, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    __hip_atomic_fetch_add(win + b + dw.crn[e], (double)cw[e], __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
             } else if (need) {
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
-                    atomicAdd(dvol + (off >> esh), c.w[e] * Ib);
+                    atomicAdd(dvol + (off >> esh), cw[e]);
                 }
             }
         }
