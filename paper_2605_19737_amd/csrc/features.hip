@@ -49,6 +49,35 @@ __global__ __launch_bounds__(NT) void k_xypass(XYArgs a, ScaleTaps taps)
     }
 }
 
+// Fixed-radius variant (x and y stencil radius R, equal) for the layouts the workloads use.
+template <int DT, int OUT_DT, int LAYOUT, int R>
+__global__ __launch_bounds__(NT) void k_xypass_r(XYArgs a, ScaleTaps taps)
+{
+    using T = XYTileR<R, TX, TY>;
+    __shared__ float F[T::NST];
+    __shared__ float Fy[T::NFY];
+    float vmax = xy_tile_r<DT, OUT_DT, LAYOUT, R, TX, TY>(a, taps, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z, F, Fy);
+    if (a.fro_pass || a.first) {
+        vmax = wave_max(vmax);
+        if ((threadIdx.x & 63) == 0) atomic_max_pos(a.fro_pass ? a.fro : a.gmax, vmax);
+    }
+}
+
+constexpr int kRFastMin = 2, kRFastMax = 10;
+
+template <int DT, int OUT_DT, int LAYOUT, int R>
+static hipError_t launch_xy_r(const XYArgs &a, const ScaleTaps &taps, hipStream_t st)
+{
+    if constexpr (R > kRFastMax) {
+        return hipErrorInvalidValue;
+    } else {
+        if (taps.ax[0].R != R) return launch_xy_r<DT, OUT_DT, LAYOUT, R + 1>(a, taps, st);
+        dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY, a.nz);
+        hipLaunchKernelGGL((k_xypass_r<DT, OUT_DT, LAYOUT, R>), grid, dim3(NT), 0, st, a, taps);
+        return hipGetLastError();
+    }
+}
+
 __global__ void k_init_scalars(float *gmax, float *fro)
 {
     if (threadIdx.x == 0) {
@@ -108,6 +137,13 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
     a.first = (scale_index == 0) && !fro_pass;
     a.fro_pass = fro_pass;
     const int odt = out.dtype, lay = out.layout;
+    const int R = taps.ax[0].R;
+    if (R == taps.ax[1].R && R >= kRFastMin && R <= kRFastMax) {
+        if (vol_dt == DVR_F32 && odt == DVR_F32 && lay == DVR_PLANAR)
+            return launch_xy_r<DVR_F32, DVR_F32, DVR_PLANAR, kRFastMin>(a, taps, st);
+        if (vol_dt == DVR_F16 && odt == DVR_F16 && lay == DVR_INTERLEAVED)
+            return launch_xy_r<DVR_F16, DVR_F16, DVR_INTERLEAVED, kRFastMin>(a, taps, st);
+    }
 #define DVR_XY(D, O, L) \
     if (vol_dt == D && odt == O && lay == L) return launch_xy<D, O, L>(a, taps, st);
     DVR_XY(DVR_F32, DVR_F32, DVR_PLANAR)
