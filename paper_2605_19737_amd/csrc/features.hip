@@ -36,6 +36,51 @@ __global__ __launch_bounds__(256) void k_zpass(const void *__restrict__ vol, flo
     zpass_voxel<DT>(vol, ws, nx, ny, nz, tz, e, (int)blockIdx.y);
 }
 
+// Fixed-radius z pass: a lane takes TZ consecutive voxels of one (x, y) column and keeps the
+// TZ + 2R inputs it needs in registers, so each input is loaded (TZ + 2R) / TZ times instead of
+// 2R + 1 times.
+template <int DT, int R, int TZ>
+__global__ __launch_bounds__(256) void k_zpass_r(const void *__restrict__ vol, float *__restrict__ ws, int nx, int ny,
+                                                 int nz, AxisTaps tz)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= plane) return;
+    const int z0 = (int)blockIdx.y * TZ;
+    const uint32_t N = plane * (uint32_t)nz;
+    const Buf b = make_buf(vol, N * ElemSize<DT>::v);
+    float col[TZ + 2 * R];
+#pragma unroll
+    for (int i = 0; i < TZ + 2 * R; ++i) col[i] = ldv<DT>(b, (uint32_t)clampi(z0 - R + i, 0, nz - 1) * plane + e);
+#pragma unroll
+    for (int k = 0; k < TZ; ++k) {
+        const int z = z0 + k;
+        if (z >= nz) break;
+        const int cls = (z == 0) ? 1 : (z == nz - 1 ? 2 : 0);
+        const Line3 o = r3<R>(tz, cls, [&](int m) { return col[k + R + m]; });
+        const uint32_t i = (uint32_t)z * plane + e;
+        ws[i] = o.g;
+        ws[N + i] = o.d1;
+        ws[2u * N + i] = o.d2;
+    }
+}
+
+constexpr int kTZ = 8;
+
+template <int DT, int R>
+static hipError_t launch_z_r(const void *vol, float *ws, const dvr_grid &g, const AxisTaps &tz, hipStream_t st)
+{
+    if constexpr (R > 10) {
+        return hipErrorInvalidValue;
+    } else {
+        if (tz.R != R) return launch_z_r<DT, R + 1>(vol, ws, g, tz, st);
+        const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
+        dim3 grid((plane + 255) / 256, (g.nz + kTZ - 1) / kTZ);
+        hipLaunchKernelGGL((k_zpass_r<DT, R, kTZ>), grid, dim3(256), 0, st, vol, ws, g.nx, g.ny, g.nz, tz);
+        return hipGetLastError();
+    }
+}
+
 constexpr int TX = 64, TY = 8;
 
 template <int DT, int OUT_DT, int LAYOUT>
@@ -109,11 +154,17 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
     (void)last_scale;
     const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
     dim3 zgrid((plane + 255) / 256, g.nz);
-    if (vol_dt == DVR_F32)
-        hipLaunchKernelGGL(k_zpass<DVR_F32>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, taps.ax[2]);
-    else
-        hipLaunchKernelGGL(k_zpass<DVR_F16>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, taps.ax[2]);
-    hipError_t e = hipGetLastError();
+    hipError_t e;
+    if (taps.ax[2].R >= 2 && taps.ax[2].R <= 10) {
+        e = (vol_dt == DVR_F32) ? launch_z_r<DVR_F32, 2>(vol, ws_fields, g, taps.ax[2], st)
+                                : launch_z_r<DVR_F16, 2>(vol, ws_fields, g, taps.ax[2], st);
+    } else {
+        if (vol_dt == DVR_F32)
+            hipLaunchKernelGGL(k_zpass<DVR_F32>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, taps.ax[2]);
+        else
+            hipLaunchKernelGGL(k_zpass<DVR_F16>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, taps.ax[2]);
+        e = hipGetLastError();
+    }
     if (e != hipSuccess) return e;
 
     XYArgs a;

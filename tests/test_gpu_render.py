@@ -313,3 +313,24 @@ def test_normalize_u16_to_f16():
     assert got.min() == 0.0 and got.max() == 1.0
     out32 = dvr.normalize(torch.from_numpy(raw.view(np.int16)).cuda(), torch.float32)
     assert rel_err(out32.cpu().numpy(), ref) <= 1e-7
+
+
+@pytest.mark.parametrize("n", [5, 8, 100003, 1 << 20])
+def test_normalize_float_inputs_ragged(n):
+    """Eq. 1 on F32 and F16 inputs of lengths below, at and off the 16-byte vector width, signed
+    values included; a constant input maps to 0 (max == min)."""
+    rng = np.random.default_rng(n)
+    x = (rng.standard_normal(n) * 3.0 - 1.0).astype(np.float32)
+    ref, _, _ = oracle.normalize(x.astype(np.float64))
+    got = dvr.normalize(torch.from_numpy(x).cuda(), torch.float32).cpu().numpy()
+    assert rel_err(got, ref) <= 2e-7
+    assert got.min() == 0.0 and got.max() == 1.0
+    g16 = dvr.normalize(torch.from_numpy(x).cuda(), torch.float16).float().cpu().numpy().astype(np.float64)
+    r16 = ref.astype(np.float16).astype(np.float64)
+    assert np.all(np.abs(g16 - r16) <= np.spacing(np.abs(r16).astype(np.float16)).astype(np.float64))
+    h = x.astype(np.float16)
+    refh, _, _ = oracle.normalize(h.astype(np.float64))
+    goth = dvr.normalize(torch.from_numpy(h).cuda(), torch.float32).cpu().numpy()
+    assert rel_err(goth, refh) <= 2e-7
+    c = np.full(n, 0.25, np.float32)
+    assert not dvr.normalize(torch.from_numpy(c).cuda(), torch.float32).cpu().numpy().any()
