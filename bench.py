@@ -35,6 +35,10 @@ PEAK_HBM_GBS = 8000.0
 FLOP_SHADED = 144
 FLOP_TRANSPARENT = 40
 RENDER_SOURCES = ["render.hip", "render_dev.hpp", "render_args.hpp", "common.hpp"]
+# Feature pass: compulsory bytes per voxel in FP32 (read I, write g, k, V) and the algorithmic flop
+# estimate per voxel at three scales (stencils, eigenvalues, vesselness; see the design notes).
+FEAT_BYTES_F32 = 24
+FEAT_FLOP_3SCALE = 830
 
 
 def log(msg):
@@ -162,6 +166,8 @@ def main():
                 "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4)}
 
     comps = {"features_voxels_per_s": vox_per_s, "features_ms": 1e3 * t_feat / K,
+             "features_hbm_frac": FEAT_BYTES_F32 * vox_per_s / (PEAK_HBM_GBS * 1e9),
+             "features_valu_frac": FEAT_FLOP_3SCALE * vox_per_s / (PEAK_FP32_TFLOPS * 1e12),
              "render_samples_per_s": render_sps, "render_ms_per_view": 1e3 * t_rend / (K * V),
              "samples_evaluated_per_step": evaluated, "samples_shaded_per_step": shaded,
              "rays_per_step": V * 1024 * 1024}
@@ -214,7 +220,9 @@ def main():
     if not args.no_cpu_baseline:
         import oracle
 
-        log("CPU baseline: FP64 oracle, full feature pass + 65536 pixels of 2 views")
+        nv_cpu = min(36, V)
+        sel = [w.cams[(i * V) // nv_cpu] for i in range(nv_cpu)]
+        log(f"CPU baseline: FP64 oracle, full feature pass + {nv_cpu} whole views of the {V}")
         threads = int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
         sp = tuple(float(np.float32(h)) for h in w.spacing)
         prm = {k: float(np.float32(v)) for k, v in w.params.items()}
@@ -222,18 +230,15 @@ def main():
         t = time.perf_counter()
         of = oracle.features(v64, sp, [float(np.float32(s)) for s in w.sigmas], c=float(np.float32(w.c)))
         t_cf = time.perf_counter() - t
-        rng = np.random.default_rng(1)
-        M = 65536
-        pix = np.stack([rng.integers(0, 2, M), rng.integers(0, 1024, M), rng.integers(0, 1024, M)], 1).astype(np.int32)
         t = time.perf_counter()
-        ro = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, [w.cams[0], w.cams[V // 4]], pix=pix)
+        ro = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, sel)
         t_cr = time.perf_counter() - t
         s_per_sample = t_cr / max(ro["nsamp"], 1)
         t_cpu_step = t_cf + s_per_sample * evaluated
         cpu = {"value": evaluated / t_cpu_step, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
-               "sample": f"FP64 oracle: full 3-scale feature pass ({t_cf:.2f} s) + {M} random pixels of 2 of the "
-                         f"{V} views ({ro['nsamp']} samples, {t_cr:.2f} s); step time = features + per-sample "
-                         f"time x the step's {evaluated} evaluated samples",
+               "sample": f"FP64 oracle: full 3-scale feature pass ({t_cf:.2f} s) + {nv_cpu} whole 1024^2 views "
+                         f"evenly spaced over the {V} ({ro['nsamp']} samples, {t_cr:.2f} s); step time = features "
+                         f"+ per-sample time x the step's {evaluated} evaluated samples",
                "features_voxels_per_s": nvox / t_cf, "render_samples_per_s": ro["nsamp"] / t_cr}
         log(f"CPU baseline {cpu['value']:.4g} samples/s on {threads} threads")
 
@@ -381,7 +386,11 @@ def leg_c5(dev, stream, dvr, torch, np, log):
     evaluated = int(cnt[0].item())
     out = {"normalize_ms": float(t[0]), "features_ms": float(t[1]), "fwd_ms_per_view": float(t[2]) / 8,
            "bwd_ms_per_view": float(t[3]) / 8, "fwd_bwd_ms_per_view": float(t[2] + t[3]) / 8,
-           "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3)}
+           "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3),
+           # compulsory bytes: normalize reads 2 B twice (reduce, scale) and writes 2 B; the feature pass
+           # reads the 2-byte volume and writes one 16-byte record per voxel
+           "normalize_hbm_frac": 6 * raw.numel() / (t[0] / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9)}
     log(f"C5: normalize {t[0]:.2f} ms, features {t[1]:.2f} ms, fwd {t[2] / 8:.2f} ms/view, bwd {t[3] / 8:.2f} ms/view")
     return out
 
