@@ -76,6 +76,16 @@ typedef struct dvr_feature_params {
                                        are re-solved in FP64; 0 disables the FP64 path */
 } dvr_feature_params;
 
+/* Brick table for exact empty-space skipping.  Brick (bx, by, bz) covers the cells
+ * [DVR_BRICK b, DVR_BRICK (b + 1)) of each axis, i.e. the voxels DVR_BRICK b .. min(DVR_BRICK (b + 1),
+ * n - 1); nb_a = ceil((n_a - 1) / DVR_BRICK) bricks per axis, nb = nbx nby nbz in all.  The table is
+ * nb (min, max) float pairs of the intensity the raymarcher samples in each brick ([nbz][nby][nbx][2],
+ * written by dvr_features), followed by ceil(nb / 32) uint32 words: one bit per brick, set by
+ * dvr_render when every intensity the trilinear interpolation can produce there maps onto TF segments
+ * of zero extinction.  Samples in such a brick have alpha = 0 exactly (Sec. 2.4 Eq. 4-6 give them no
+ * weight), so the forward raymarch passes them without fetching features; the result is unchanged. */
+#define DVR_BRICK 4
+
 typedef struct dvr_features_buf {
     void *grad;   /* device; see dvr_layout */
     void *kappa;  /* device, PLANAR only */
@@ -83,6 +93,13 @@ typedef struct dvr_features_buf {
     float *gmax;  /* device scalar: max over voxels of |grad I|_2 (the |grad I|_max of Eq. 4) */
     int32_t dtype;  /* DVR_F32 or DVR_F16 (storage type; arithmetic is FP32) */
     int32_t layout; /* dvr_layout */
+    float *bricks;  /* device brick table of dvr_bricks_bytes() bytes, 8-byte aligned, or NULL.  Its
+                       (min, max) pairs are written by dvr_features from the intensity the raymarcher
+                       samples (the volume passed to dvr_features for PLANAR, the records' I for
+                       INTERLEAVED); when non-NULL, dvr_render writes the empty-brick bits for its TF
+                       and skips those bricks (the volume must then be the one the table was built
+                       from, and renders sharing one table must be ordered on one stream).
+                       dvr_render_backward and the batched launch do not use it. */
 } dvr_features_buf;
 
 typedef struct dvr_tf {
@@ -143,6 +160,10 @@ dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t 
  * vol: device [nz][ny][nx] of vol_dtype (DVR_F32 or DVR_F16).  ws: device workspace of at least
  * dvr_features_workspace() bytes.  out: see dvr_features_buf (F32 or F16, PLANAR or INTERLEAVED). */
 dvr_status dvr_features_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes);
+/* Number of bricks nb = nbx * nby * nbz, and the byte size 8 nb + 4 ceil(nb / 32) of the brick table,
+ * for this grid. */
+dvr_status dvr_bricks_count(const dvr_grid *grid, int64_t *count);
+dvr_status dvr_bricks_bytes(const dvr_grid *grid, size_t *bytes);
 dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_feature_params *fp,
                         const dvr_features_buf *out, void *ws, size_t ws_bytes, hipStream_t stream);
 

@@ -9,6 +9,7 @@ every arithmetic step runs in the HIP kernels of libdvr.so (see include/dvr.h).
 from __future__ import annotations
 
 import ctypes as C
+import math
 from dataclasses import dataclass
 
 import torch
@@ -76,6 +77,7 @@ class Features:
     layout: int
     shape: tuple
     spacing: tuple
+    bricks: torch.Tensor | None = None  # brick table (flat float32: (min, max) pairs, then mask words), or None
 
     @property
     def dtype(self):
@@ -84,7 +86,17 @@ class Features:
     def buf(self):
         return abi.FeaturesBuf(self.grad.data_ptr(), self.kappa.data_ptr() if self.kappa is not None else None,
                                self.ves.data_ptr() if self.ves is not None else None, self.gmax.data_ptr(),
-                               _dt(self.grad), self.layout)
+                               _dt(self.grad), self.layout,
+                               self.bricks.data_ptr() if self.bricks is not None else None)
+
+    def brick_minmax(self):
+        """[nbz][nby][nbx][2] view of the (min, max) part of the brick table."""
+        nb = brick_dims(self.shape)
+        return self.bricks[:2 * nb[0] * nb[1] * nb[2]].view(*nb, 2)
+
+    def without_bricks(self):
+        """The same fields with no brick table (the raymarch then visits every sample)."""
+        return Features(self.grad, self.kappa, self.ves, self.gmax, self.layout, self.shape, self.spacing, None)
 
 
 def _fparams(sigmas, alpha, beta, c, eig_gap):
@@ -98,7 +110,13 @@ def _fparams(sigmas, alpha, beta, c, eig_gap):
     return fp
 
 
-def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANAR, device="cuda"):
+def brick_dims(shape_zyx):
+    """(nbz, nby, nbx) of the brick table for a [nz][ny][nx] volume."""
+    return tuple((n - 1 + abi.DVR_BRICK - 1) // abi.DVR_BRICK for n in shape_zyx)
+
+
+def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANAR, device="cuda", bricks=True):
+    """Uninitialized feature fields; bricks=True also allocates the brick table for empty-space skipping."""
     nz, ny, nx = shape_zyx
     if layout == abi.DVR_PLANAR:
         grad = torch.empty((3, nz, ny, nx), dtype=dtype, device=device)
@@ -108,7 +126,9 @@ def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANA
         grad = torch.empty((nz, ny, nx, 8), dtype=dtype, device=device)
         kappa = ves = None
     gmax = torch.empty(1, dtype=torch.float32, device=device)
-    return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing))
+    nb = math.prod(brick_dims(shape_zyx))
+    bt = torch.empty(2 * nb + (nb + 31) // 32, dtype=torch.float32, device=device) if bricks else None
+    return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing), bt)
 
 
 def features_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2):

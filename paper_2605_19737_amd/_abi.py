@@ -18,6 +18,7 @@ STATUS = {0: "DVR_OK", -1: "DVR_E_INVALID_ARG", -2: "DVR_E_NULL", -3: "DVR_E_ALI
 DVR_F32, DVR_F16, DVR_U16 = 0, 1, 2
 DVR_PLANAR, DVR_INTERLEAVED = 0, 1
 DVR_MAX_SIGMA = 8
+DVR_BRICK = 4
 
 
 class Grid(C.Structure):
@@ -32,7 +33,7 @@ class FeatureParams(C.Structure):
 
 class FeaturesBuf(C.Structure):
     _fields_ = [("grad", C.c_void_p), ("kappa", C.c_void_p), ("ves", C.c_void_p), ("gmax", C.c_void_p),
-                ("dtype", C.c_int32), ("layout", C.c_int32)]
+                ("dtype", C.c_int32), ("layout", C.c_int32), ("bricks", C.c_void_p)]
 
 
 class TF(C.Structure):
@@ -97,6 +98,8 @@ def load():
     L.dvr_normalize_workspace.argtypes = [i64, P(sz)]
     L.dvr_normalize.argtypes = [vp, i32, vp, i32, i64, vp, sz, vp]
     L.dvr_features_workspace.argtypes = [P(Grid), P(FeatureParams), P(sz)]
+    L.dvr_bricks_count.argtypes = [P(Grid), P(i64)]
+    L.dvr_bricks_bytes.argtypes = [P(Grid), P(sz)]
     L.dvr_features.argtypes = [vp, i32, P(Grid), P(FeatureParams), P(FeaturesBuf), vp, sz, vp]
     L.dvr_render.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32, vp,
                              P(RayState), vp]
@@ -107,7 +110,7 @@ def load():
     L.dvr_batch_check.argtypes = [vp, vp]
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
-    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_features",
+    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_features",
                  "dvr_render", "dvr_render_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32

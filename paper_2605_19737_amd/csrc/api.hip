@@ -95,8 +95,11 @@ dvr_status check_feat_buf(const dvr_features_buf *f, bool need_writable)
         if (!f->kappa || !f->ves) return fail(DVR_E_NULL, "planar features need kappa and ves");
         if (!aligned16(f->kappa) || !aligned16(f->ves)) return fail(DVR_E_ALIGN, "kappa/ves not 16-byte aligned");
     }
+    if (((uintptr_t)f->bricks & 7u) != 0) return fail(DVR_E_ALIGN, "bricks is not 8-byte aligned");
     return DVR_OK;
 }
+
+int nbricks(int n) { return (n - 1 + DVR_BRICK - 1) / DVR_BRICK; }
 
 void axis_taps(double sigma_vox, double h, dvr::AxisTaps &t)
 {
@@ -168,6 +171,25 @@ dvr_status dvr_features_workspace(const dvr_grid *grid, const dvr_feature_params
     return DVR_OK;
 }
 
+dvr_status dvr_bricks_count(const dvr_grid *grid, int64_t *count)
+{
+    dvr_status s = check_grid(grid);
+    if (s) return s;
+    if (!count) return fail(DVR_E_NULL, "count is NULL");
+    *count = (int64_t)nbricks(grid->nx) * nbricks(grid->ny) * nbricks(grid->nz);
+    return DVR_OK;
+}
+
+dvr_status dvr_bricks_bytes(const dvr_grid *grid, size_t *bytes)
+{
+    int64_t nb = 0;
+    dvr_status s = dvr_bricks_count(grid, &nb);
+    if (s) return s;
+    if (!bytes) return fail(DVR_E_NULL, "bytes is NULL");
+    *bytes = (size_t)nb * 8u + (size_t)((nb + 31) / 32) * 4u;
+    return DVR_OK;
+}
+
 dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_feature_params *fp,
                         const dvr_features_buf *out, void *ws, size_t ws_bytes, hipStream_t stream)
 {
@@ -198,6 +220,10 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
                                            scalars, pass == 0, stream);
             if (e != hipSuccess) return dev_fail(e, "features launch");
         }
+    }
+    if (out->bricks) {
+        e = dvr::launch_bricks(vol, vol_dtype, *grid, *out, stream);
+        if (e != hipSuccess) return dev_fail(e, "brick table launch");
     }
     return DVR_OK;
 }
@@ -255,6 +281,10 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
     a.feat.gmax = feat->gmax;
     a.feat.dtype = feat->dtype;
     a.feat.layout = feat->layout;
+    a.feat.bricks = feat->bricks;
+    a.feat.nb[0] = nbricks(grid->nx);
+    a.feat.nb[1] = nbricks(grid->ny);
+    a.feat.nb[2] = nbricks(grid->nz);
     a.grid.n[0] = grid->nx;
     a.grid.n[1] = grid->ny;
     a.grid.n[2] = grid->nz;

@@ -235,6 +235,8 @@ __global__ __launch_bounds__(256, 4) void k_batch(BatchArgs A)
             f.gmax = V.gmax;
             f.dtype = DT;
             f.layout = LAYOUT;
+            f.bricks = nullptr;  // the batched launch builds no brick tables
+            f.nb[0] = f.nb[1] = f.nb[2] = 0;
             KGrid g;
             for (int k = 0; k < 3; ++k) {
                 g.n[k] = V.n[k];

@@ -92,6 +92,7 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
                                  const dvr_features_buf &out, float *ws_fields, float *ws_scalars,
                                  bool fro_pass, hipStream_t st);
 hipError_t launch_init_scalars(float *gmax, float *ws_scalars, hipStream_t st);
+hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const dvr_features_buf &out, hipStream_t st);
 
 hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, int64_t n, uint32_t *ws,
                             hipStream_t st);

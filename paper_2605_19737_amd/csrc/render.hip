@@ -187,7 +187,41 @@ static hipError_t launch_any(const RenderArgs &a, hipStream_t st, bool bwd)
     return hipSuccess;
 }
 
-hipError_t launch_render(const RenderArgs &a, hipStream_t st) { return launch_any(a, st, false); }
+// Empty-brick bits for one TF: brick i is empty when brick_empty() holds for its (min, max); a wave
+// covers 64 bricks and writes the two 32-bit words of its ballot.
+__global__ __launch_bounds__(256) void k_brick_mask(const float *__restrict__ bricks, int nb, KTF tf)
+{
+    __shared__ TFShared<64> sh;
+    float kx[64];
+    tf_load<64>(sh, kx, tf);
+    __syncthreads();
+    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    bool e = false;
+    if (i < nb) e = brick_empty<64>(sh, kx, bricks[2 * i], bricks[2 * i + 1]);
+    const uint64_t bal = __ballot(e);
+    const int w0 = (int)(blockIdx.x * 256u + (threadIdx.x & ~63u)) / 32;  // first word of this wave
+    const int nw = (nb + 31) / 32;
+    uint32_t *mask = reinterpret_cast<uint32_t *>(const_cast<float *>(bricks) + 2 * nb);
+    const int lane = threadIdx.x & 63;
+    if (lane == 0 && w0 < nw) mask[w0] = (uint32_t)bal;
+    if (lane == 1 && w0 + 1 < nw) mask[w0 + 1] = (uint32_t)(bal >> 32);
+}
+
+hipError_t launch_brick_mask(const RenderArgs &a, hipStream_t st)
+{
+    const int nb = a.feat.nb[0] * a.feat.nb[1] * a.feat.nb[2];
+    hipLaunchKernelGGL(k_brick_mask, dim3((nb + 255) / 256), dim3(256), 0, st, a.feat.bricks, nb, a.tf);
+    return hipGetLastError();
+}
+
+hipError_t launch_render(const RenderArgs &a, hipStream_t st)
+{
+    if (a.feat.bricks) {
+        const hipError_t e = launch_brick_mask(a, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_any(a, st, false);
+}
 hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st) { return launch_any(a, st, true); }
 
 }  // namespace dvr

@@ -20,6 +20,8 @@ struct KFeat {
     const void *grad, *kappa, *ves;
     const float *gmax;
     int32_t dtype, layout;
+    const float *bricks;  // [nb2][nb1][nb0][2] intensity (min, max) per brick, or null (no skipping)
+    int32_t nb[3];
 };
 
 struct KGrid {

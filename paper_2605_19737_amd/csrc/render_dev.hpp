@@ -98,12 +98,15 @@ __device__ __forceinline__ RayGeo ray_setup(const KCam cam, int pi, int pj, cons
 
 // ------------------------------------------------------------------------------------------------
 // TF in LDS: knot x, value (R, G, B, tau), slope to the next knot (0 after the last), 1/width.
+// nzp: prefix counts over the extended segments e = -1 (below the first knot) .. K-1 (at or above
+// the last) of "the extinction is not identically zero on e": nzp[0] = 0, nzp[j + 1] = nzp[j] + nz(j - 1).
 template <int KMAX>
 struct TFShared {
     float4 v[KMAX];
     float4 s[KMAX];
     float x[KMAX];
     float iw[KMAX];
+    int nzp[KMAX + 2];
 };
 
 template <int KMAX>
@@ -127,8 +130,40 @@ __device__ __forceinline__ void tf_load(TFShared<KMAX> &sh, float (&kx)[KMAX], c
             }
         }
     }
+    if (threadIdx.x == 0) {
+        const float4 *r = reinterpret_cast<const float4 *>(tf.rgba);
+        int c = 0;
+        sh.nzp[0] = 0;
+        for (int e = -1; e < K; ++e) {
+            const bool nz = (e < 0) ? (r[0].w != 0.f) : (e == K - 1 ? r[K - 1].w != 0.f : (r[e].w != 0.f || r[e + 1].w != 0.f));
+            c += nz ? 1 : 0;
+            sh.nzp[e + 2] = c;
+        }
+    }
 #pragma unroll
     for (int i = 0; i < KMAX; ++i) kx[i] = (i < K) ? tf.knots[i] : INFINITY;
+}
+
+// extended TF segment of x: -1 below the first knot, else the index of the last knot <= x
+template <int KMAX>
+__device__ __forceinline__ int tf_seg(const float (&kx)[KMAX], float x)
+{
+    int c = 0;
+#pragma unroll
+    for (int i = 0; i < KMAX; ++i) c += (x >= kx[i]) ? 1 : 0;
+    return c - 1;
+}
+
+// True when every intensity the trilinear interpolation can produce from corner values in
+// [lo, hi] falls on TF segments whose extinction is identically zero.  The interval is widened by
+// 2^-18 max(|lo|, |hi|): the FP32 weights and the fma chain of the interpolation stay within
+// ~2^-19 of the range of the corner values.
+template <int KMAX>
+__device__ __forceinline__ bool brick_empty(const TFShared<KMAX> &sh, const float (&kx)[KMAX], float lo, float hi)
+{
+    const float d = fmaxf(fabsf(lo), fabsf(hi)) * 3.814697265625e-6f + 1e-30f;
+    const int a = tf_seg<KMAX>(kx, lo - d), b = tf_seg<KMAX>(kx, hi + d);
+    return sh.nzp[b + 2] - sh.nzp[a + 1] == 0;
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -341,7 +376,36 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
         float dk = (r.N == 1) ? r.dlast : r.delta;
         CornerCache<LAYOUT, DT> cc;
         cc.reset();
+        // empty-space skipping: a sample in a brick whose bit is set has alpha = 0 exactly; it is
+        // passed with Tprev and last set as the full sample would set them, without fetching
+        static_assert(DVR_BRICK == 4, "brick index = fixed-point position >> (32 + 2)");
+        const bool skip = feat.bricks != nullptr;
+        const int nbt = feat.nb[0] * feat.nb[1] * feat.nb[2];
+        Buf bm;
+        if (skip) bm = make_buf(feat.bricks + 2 * nbt, (uint32_t)((nbt + 31) / 32) * 4u);
+        int cur_brick = -1;
+        bool cur_empty = false;
         for (int k = 0; k < r.N; ++k) {
+            if (skip) {
+                const int bi = ((int)(q[2] >> 34) * feat.nb[1] + (int)(q[1] >> 34)) * feat.nb[0] + (int)(q[0] >> 34);
+                if (bi != cur_brick) {
+                    cur_brick = bi;
+                    const uint32_t wd = __builtin_amdgcn_raw_buffer_load_b32(bm.r, (uint32_t)(bi >> 5) * 4u, 0, 0);
+                    cur_empty = ((wd >> (bi & 31)) & 1u) != 0u;
+                }
+                if (cur_empty) {
+                    Tprev = T;
+                    last = k;
+                    if (k + 1 == r.N - 1) {
+                        dq[0] = r.dql[0]; dq[1] = r.dql[1]; dq[2] = r.dql[2];
+                        dk = r.dlast;
+                    }
+                    q[0] += dq[0];
+                    q[1] += dq[1];
+                    q[2] += dq[2];
+                    continue;
+                }
+            }
             Corners c;
             corner_setup(q, vx.sx, vx.sy, vx.sz, c);
             Chan ch;

@@ -196,3 +196,20 @@ def test_batch_create_rejects(L, kind, code):
     s, msg = _status(L, "dvr_batch_create", C.byref(d), C.byref(plan))
     assert s == code and msg and not plan.value
     assert L.dvr_batch_destroy(None) == 0
+
+
+def test_bricks_count_and_alignment(L):
+    """nb_a = ceil((n_a - 1) / DVR_BRICK) bricks per axis; a brick table that is not 8-byte aligned is
+    rejected before anything is enqueued."""
+    cnt = C.c_int64()
+    assert L.dvr_bricks_count(C.byref(_grid(8, 9, 10)), C.byref(cnt)) == 0
+    assert cnt.value == 2 * 2 * 3  # cells 7, 8, 9 -> 2, 2, 3 bricks of 4
+    assert L.dvr_bricks_count(C.byref(_grid(2, 2, 2)), C.byref(cnt)) == 0 and cnt.value == 1
+    assert L.dvr_bricks_count(C.byref(_grid(1, 9, 10)), C.byref(cnt)) == -1
+    n = C.c_size_t()
+    assert L.dvr_bricks_bytes(C.byref(_grid(8, 9, 10)), C.byref(n)) == 0 and n.value == 12 * 8 + 4
+    assert L.dvr_bricks_bytes(C.byref(_grid(130, 9, 10)), C.byref(n)) == 0 and n.value == 198 * 8 + 7 * 4  # 33 x 2 x 3
+    fb = abi.FeaturesBuf(FAKE, FAKE, FAKE, FAKE, abi.DVR_F32, abi.DVR_PLANAR, FAKE + 4)
+    s, msg = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fp()),
+                     C.byref(fb), C.c_void_p(FAKE), 1 << 30, None)
+    assert s == -3 and "bricks" in msg
