@@ -387,12 +387,28 @@ def leg_c5(dev, stream, dvr, torch, np, log):
             times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(4)])
     t = np.median(np.array(times), axis=0)
     evaluated = int(cnt[0].item())
+    # automatic tissue windows on the normalized volume: histogram (2 B/voxel read), peaks, TF
+    ht = []
+    for it in range(4):
+        e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
+        e0.record(stream)
+        h, _ = dvr.histogram(v16, 0.0)
+        e1.record(stream)
+        buf, pk = dvr.tissue_peaks(h, 2)
+        kn_t, tf_t = dvr.tissue_tf(buf, [(0.2, 0.4, 1.0), (0.9, 0.6, 0.5), (1.0, 0.95, 0.85)], (0.1, 0.3, 0.6))
+        e2.record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            ht.append((e0.elapsed_time(e1), e1.elapsed_time(e2)))
+    th = float(np.median([x[0] for x in ht]))
     out = {"normalize_ms": float(t[0]), "features_ms": float(t[1]), "fwd_ms_per_view": float(t[2]) / 8,
            "bwd_ms_per_view": float(t[3]) / 8, "fwd_bwd_ms_per_view": float(t[2] + t[3]) / 8,
            "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3),
            # compulsory bytes: normalize reads 2 B twice (reduce, scale) and writes 2 B; the feature pass
            # reads the 2-byte volume and writes one 16-byte record per voxel
            "normalize_hbm_frac": 6 * raw.numel() / (t[0] / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "histogram_ms": th, "histogram_hbm_frac": 2 * raw.numel() / (th / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "tissue_peaks": pk,
            "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9)}
     log(f"C5: normalize {t[0]:.2f} ms, features {t[1]:.2f} ms, fwd {t[2] / 8:.2f} ms/view, bwd {t[3] / 8:.2f} ms/view")
     return out

@@ -167,6 +167,44 @@ dvr_status dvr_bricks_bytes(const dvr_grid *grid, size_t *bytes);
 dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_feature_params *fp,
                         const dvr_features_buf *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Automatic tissue windows (Sec. 2.2: a 256-bin density analysis of I_norm shows three tissue peaks;
+ * Sec. 3.1, Table 2: target windows CSF 0.05..0.12, GM 0.12..0.18, WM > 0.18).
+ * Histogram: counts of the values x > floor of a normalized volume in bin floor(256 x) clamped to
+ * [0, 255] (x = 1 falls in the last bin).  vol: device, DVR_F32 or DVR_F16, 16-byte aligned, n < 2^32
+ * values; hist: device uint32[256], overwritten; used: device uint32 (the number counted) or NULL. */
+#define DVR_HIST_BINS 256
+dvr_status dvr_histogram(const void *vol, int32_t dtype, int64_t n, float floor_, uint32_t *hist, uint32_t *used,
+                         hipStream_t stream);
+
+/* The three tissue peaks of a histogram: the local maxima of the [1, 2, 1]-smoothed counts
+ * (S[b] > S[b-1] and S[b] >= S[b+1], clamped ends), taken greedily by S (lower bin first on a tie) at
+ * least min_sep bins apart, at most three, ordered by bin as CSF, GM, WM; peak = (bin + 1/2) / 256;
+ * a missing peak has bin -1 and peak -1; in_window tells whether the peak lies in its Table 2
+ * window (CSF [0.05, 0.12), GM [0.12, 0.18), WM (0.18, 1]). */
+typedef struct dvr_peaks {
+    int32_t bin[3];
+    float peak[3];
+    int32_t in_window[3];
+} dvr_peaks;
+/* hist: device uint32[256]; out: device dvr_peaks, overwritten; min_sep >= 1. */
+dvr_status dvr_tissue_peaks(const uint32_t *hist, int32_t min_sep, dvr_peaks *out, hipStream_t stream);
+
+/* A transfer function from the peaks (the "zero-shot" TF of Sec. 3.1): 8 knots
+ * (0, 0.05, m_CSF, m_GM, m_WM, u, u + 1/256, 1), m_c the peak (a missing one: the window centre
+ * 0.085, 0.15, 0.24), kept strictly increasing at least one bin apart with m_WM <= 1 - 3/256, and
+ * u = m_WM + (m_WM - m_GM) within [m_WM + 1/256, 1 - 2/256].  RGBA: extinction 0 at the first two
+ * knots (low-intensity bone and air clipped, Sec. 2.2), rgb[c] / tau[c] at the peaks, the WM plateau
+ * up to u, rgb_hi / tau_hi above it (tau_hi = 0 also clips extracranial fat and enhancing tissue). */
+typedef struct dvr_tissue_tf_params {
+    float rgb[3][3]; /* CSF, GM, WM colours in [0, 1] */
+    float tau[3];    /* their extinctions per mm, >= 0 */
+    float rgb_hi[3];
+    float tau_hi;
+} dvr_tissue_tf_params;
+/* peaks: device dvr_peaks; knots: device float[8]; rgba: device float[8][4] (16-byte aligned). */
+dvr_status dvr_tissue_tf(const dvr_peaks *peaks, const dvr_tissue_tf_params *params, float *knots, float *rgba,
+                         hipStream_t stream);
+
 /* Raymarch (Sec. 2.4 Eq. 4-6), one ray per pixel of each camera.  The box [0,(n-1)h] is clipped
  * by the slab method; the chord [tn, tf] is cut into N = ceil(L / delta) segments of
  * delta = step_vox * min(h) (the last one shorter) and sampled at segment midpoints.  Each sample

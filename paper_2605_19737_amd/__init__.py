@@ -229,6 +229,42 @@ def normalize(raw, out_dtype=torch.float16):
     return out
 
 
+def histogram(vol, floor=0.0):
+    """dvr_histogram (Sec. 2.2): 256-bin counts of the normalized values > floor -> (int64 [256] device
+    tensor, number used)."""
+    _require_cuda(vol)
+    h = torch.empty(256, dtype=torch.int32, device=vol.device)
+    used = torch.empty(1, dtype=torch.int32, device=vol.device)
+    abi.check(lib().dvr_histogram(_ptr(vol), _dt(vol), vol.numel(), float(floor), _ptr(h), _ptr(used), _stream()))
+    return h.long() & 0xFFFFFFFF, int(used.long().item() & 0xFFFFFFFF)
+
+
+def tissue_peaks(hist, min_sep=2):
+    """dvr_tissue_peaks: the three tissue peaks of a 256-bin histogram (device tensor of counts) ->
+    (device dvr_peaks buffer, dict(bin, peak, in_window))."""
+    _require_cuda(hist)
+    h = hist.to(torch.int64).clamp_(0, 0xFFFFFFFF).to(torch.int32) if hist.dtype != torch.int32 else hist.contiguous()
+    buf = torch.empty(C.sizeof(abi.Peaks), dtype=torch.uint8, device=hist.device)
+    abi.check(lib().dvr_tissue_peaks(_ptr(h), int(min_sep), _ptr(buf), _stream()))
+    pk = abi.Peaks.from_buffer_copy(bytes(buf.cpu().numpy()))
+    return buf, dict(bin=list(pk.bin), peak=list(pk.peak), in_window=[bool(x) for x in pk.in_window])
+
+
+def tissue_tf(peaks_buf, colours, taus, tau_hi=0.0, colour_hi=(1.0, 1.0, 1.0)):
+    """dvr_tissue_tf: the 8-knot TF of the peaks -> (knots [8], rgba [8][4]) device tensors."""
+    p = abi.TissueTFParams()
+    for c in range(3):
+        for k in range(3):
+            p.rgb[c][k] = float(colours[c][k])
+        p.tau[c] = float(taus[c])
+        p.rgb_hi[c] = float(colour_hi[c])
+    p.tau_hi = float(tau_hi)
+    knots = torch.empty(8, dtype=torch.float32, device=peaks_buf.device)
+    rgba = torch.empty((8, 4), dtype=torch.float32, device=peaks_buf.device)
+    abi.check(lib().dvr_tissue_tf(_ptr(peaks_buf), C.byref(p), _ptr(knots), _ptr(rgba), _stream()))
+    return knots, rgba
+
+
 class DVRRender(torch.autograd.Function):
     """rgba = render(vol, TF values) with gradients for the voxel intensities and the TF values
     (knot positions, gradient, k and V are held constant).  The backward is the hand-written adjoint

@@ -36,6 +36,14 @@ class FeaturesBuf(C.Structure):
                 ("dtype", C.c_int32), ("layout", C.c_int32), ("bricks", C.c_void_p)]
 
 
+class Peaks(C.Structure):
+    _fields_ = [("bin", C.c_int32 * 3), ("peak", C.c_float * 3), ("in_window", C.c_int32 * 3)]
+
+
+class TissueTFParams(C.Structure):
+    _fields_ = [("rgb", (C.c_float * 3) * 3), ("tau", C.c_float * 3), ("rgb_hi", C.c_float * 3), ("tau_hi", C.c_float)]
+
+
 class TF(C.Structure):
     _fields_ = [("K", C.c_int32), ("knots", C.c_void_p), ("rgba", C.c_void_p)]
 
@@ -99,6 +107,9 @@ def load():
     L.dvr_normalize.argtypes = [vp, i32, vp, i32, i64, vp, sz, vp]
     L.dvr_features_workspace.argtypes = [P(Grid), P(FeatureParams), P(sz)]
     L.dvr_bricks_count.argtypes = [P(Grid), P(i64)]
+    L.dvr_histogram.argtypes = [vp, i32, i64, C.c_float, vp, vp, vp]
+    L.dvr_tissue_peaks.argtypes = [vp, i32, vp, vp]
+    L.dvr_tissue_tf.argtypes = [vp, P(TissueTFParams), vp, vp, vp]
     L.dvr_bricks_bytes.argtypes = [P(Grid), P(sz)]
     L.dvr_features.argtypes = [vp, i32, P(Grid), P(FeatureParams), P(FeaturesBuf), vp, sz, vp]
     L.dvr_render.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32, vp,
@@ -110,7 +121,7 @@ def load():
     L.dvr_batch_check.argtypes = [vp, vp]
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
-    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_features",
+    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
                  "dvr_render", "dvr_render_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32

@@ -161,6 +161,45 @@ dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t 
     return e == hipSuccess ? DVR_OK : dev_fail(e, "normalize launch");
 }
 
+dvr_status dvr_histogram(const void *vol, int32_t dtype, int64_t n, float floor_, uint32_t *hist, uint32_t *used,
+                         hipStream_t stream)
+{
+    if (!vol || !hist) return fail(DVR_E_NULL, "vol and hist must be non-NULL");
+    if (!aligned16(vol) || ((uintptr_t)hist & 3u) || ((uintptr_t)used & 3u))
+        return fail(DVR_E_ALIGN, "vol must be 16-byte aligned, hist and used 4-byte aligned");
+    if (dtype != DVR_F32 && dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "dtype must be F32 or F16");
+    if (n <= 0 || n >= ((int64_t)1 << 32)) return fail(DVR_E_INVALID_ARG, "n must be in [1, 2^32)");
+    if (!isfinite(floor_)) return fail(DVR_E_INVALID_ARG, "floor must be finite");
+    hipError_t e = dvr::launch_histogram(vol, dtype, n, floor_, hist, used, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "histogram launch");
+}
+
+dvr_status dvr_tissue_peaks(const uint32_t *hist, int32_t min_sep, dvr_peaks *out, hipStream_t stream)
+{
+    if (!hist || !out) return fail(DVR_E_NULL, "hist and out must be non-NULL");
+    if (((uintptr_t)hist & 3u) || ((uintptr_t)out & 3u)) return fail(DVR_E_ALIGN, "hist and out must be 4-byte aligned");
+    if (min_sep < 1 || min_sep > 255) return fail(DVR_E_INVALID_ARG, "min_sep must be in [1, 255]");
+    hipError_t e = dvr::launch_peaks(hist, min_sep, out, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "peaks launch");
+}
+
+dvr_status dvr_tissue_tf(const dvr_peaks *peaks, const dvr_tissue_tf_params *params, float *knots, float *rgba,
+                         hipStream_t stream)
+{
+    if (!peaks || !params || !knots || !rgba) return fail(DVR_E_NULL, "peaks, params, knots and rgba must be non-NULL");
+    if (((uintptr_t)peaks & 3u) || ((uintptr_t)knots & 3u) || !aligned16(rgba))
+        return fail(DVR_E_ALIGN, "peaks and knots 4-byte, rgba 16-byte aligned");
+    for (int c = 0; c < 3; ++c) {
+        if (!(params->tau[c] >= 0.f) || !isfinite(params->tau[c])) return fail(DVR_E_INVALID_ARG, "tau must be >= 0");
+        for (int k = 0; k < 3; ++k)
+            if (!(params->rgb[c][k] >= 0.f && params->rgb[c][k] <= 1.f) || !(params->rgb_hi[k] >= 0.f && params->rgb_hi[k] <= 1.f))
+                return fail(DVR_E_INVALID_ARG, "colours must be in [0, 1]");
+    }
+    if (!(params->tau_hi >= 0.f) || !isfinite(params->tau_hi)) return fail(DVR_E_INVALID_ARG, "tau_hi must be >= 0");
+    hipError_t e = dvr::launch_tissue_tf(peaks, *params, knots, rgba, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "tissue TF launch");
+}
+
 dvr_status dvr_features_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes)
 {
     dvr_status s = check_grid(grid);

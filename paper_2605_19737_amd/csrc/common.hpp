@@ -97,6 +97,12 @@ hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const d
 hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, int64_t n, uint32_t *ws,
                             hipStream_t st);
 
+hipError_t launch_histogram(const void *vol, int dt, int64_t n, float floor_, uint32_t *hist, uint32_t *used,
+                            hipStream_t st);
+hipError_t launch_peaks(const uint32_t *hist, int min_sep, dvr_peaks *out, hipStream_t st);
+hipError_t launch_tissue_tf(const dvr_peaks *pk, const dvr_tissue_tf_params &p, float *knots, float *rgba,
+                            hipStream_t st);
+
 struct RenderArgs;
 hipError_t launch_render(const RenderArgs &a, hipStream_t st);
 hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st);
