@@ -167,6 +167,19 @@ dvr_status dvr_bricks_bytes(const dvr_grid *grid, size_t *bytes);
 dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_feature_params *fp,
                         const dvr_features_buf *out, void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* Optional denoise pre-pass (Sec. 5.3: spatial smoothing or median filtering as an optional compute
+ * pass before the feature pass).
+ *   DVR_DENOISE_MEDIAN3  3x3x3 median with clamped indices (exact: the result is one of the inputs);
+ *   DVR_DENOISE_GAUSS    separable sampled, normalized Gaussian of sigma_mm (per-axis radius
+ *                        floor(3 sigma/h + 1/2) <= DVR_MAX_RADIUS, clamped indices), FP32 arithmetic.
+ * vol, out: device [nz][ny][nx] of dtype (DVR_F32 or DVR_F16, rounded to nearest even), distinct,
+ * 16-byte aligned; ws: device workspace of dvr_denoise_workspace() bytes (GAUSS: two FP32 volumes;
+ * MEDIAN3: none, ws may be NULL). */
+typedef enum dvr_denoise_mode { DVR_DENOISE_GAUSS = 0, DVR_DENOISE_MEDIAN3 = 1 } dvr_denoise_mode;
+dvr_status dvr_denoise_workspace(const dvr_grid *grid, int32_t mode, size_t *bytes);
+dvr_status dvr_denoise(const void *vol, int32_t dtype, const dvr_grid *grid, int32_t mode, float sigma_mm, void *out,
+                       void *ws, size_t ws_bytes, hipStream_t stream);
+
 /* Automatic tissue windows (Sec. 2.2: a 256-bin density analysis of I_norm shows three tissue peaks;
  * Sec. 3.1, Table 2: target windows CSF 0.05..0.12, GM 0.12..0.18, WM > 0.18).
  * Histogram: counts of the values x > floor of a normalized volume in bin floor(256 x) clamped to

@@ -229,6 +229,21 @@ def normalize(raw, out_dtype=torch.float16):
     return out
 
 
+def denoise(vol, spacing, mode="median3", sigma_mm=1.0, out=None):
+    """dvr_denoise (Sec. 5.3): 3x3x3 median (mode "median3") or separable Gaussian of sigma_mm
+    (mode "gauss") of vol [nz][ny][nx] (float32 or float16); returns a new tensor (or out)."""
+    _require_cuda(vol)
+    m = abi.DVR_DENOISE_MEDIAN3 if mode == "median3" else abi.DVR_DENOISE_GAUSS
+    g = grid_struct(vol.shape, spacing)
+    n = C.c_size_t()
+    abi.check(lib().dvr_denoise_workspace(C.byref(g), m, C.byref(n)))
+    ws = torch.empty(max(n.value, 16), dtype=torch.uint8, device=vol.device)
+    out = torch.empty_like(vol) if out is None else out
+    abi.check(lib().dvr_denoise(_ptr(vol), _dt(vol), C.byref(g), m, float(sigma_mm), _ptr(out), _ptr(ws), n.value,
+                                _stream()))
+    return out
+
+
 def histogram(vol, floor=0.0):
     """dvr_histogram (Sec. 2.2): 256-bin counts of the normalized values > floor -> (int64 [256] device
     tensor, number used)."""

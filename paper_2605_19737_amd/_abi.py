@@ -19,6 +19,7 @@ DVR_F32, DVR_F16, DVR_U16 = 0, 1, 2
 DVR_PLANAR, DVR_INTERLEAVED = 0, 1
 DVR_MAX_SIGMA = 8
 DVR_BRICK = 4
+DVR_DENOISE_GAUSS, DVR_DENOISE_MEDIAN3 = 0, 1
 
 
 class Grid(C.Structure):
@@ -108,6 +109,8 @@ def load():
     L.dvr_features_workspace.argtypes = [P(Grid), P(FeatureParams), P(sz)]
     L.dvr_bricks_count.argtypes = [P(Grid), P(i64)]
     L.dvr_histogram.argtypes = [vp, i32, i64, C.c_float, vp, vp, vp]
+    L.dvr_denoise_workspace.argtypes = [P(Grid), i32, P(sz)]
+    L.dvr_denoise.argtypes = [vp, i32, P(Grid), i32, C.c_float, vp, vp, sz, vp]
     L.dvr_tissue_peaks.argtypes = [vp, i32, vp, vp]
     L.dvr_tissue_tf.argtypes = [vp, P(TissueTFParams), vp, vp, vp]
     L.dvr_bricks_bytes.argtypes = [P(Grid), P(sz)]
@@ -121,7 +124,7 @@ def load():
     L.dvr_batch_check.argtypes = [vp, vp]
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
-    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
+    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_denoise_workspace", "dvr_denoise", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
                  "dvr_render", "dvr_render_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32

@@ -161,6 +161,47 @@ dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t 
     return e == hipSuccess ? DVR_OK : dev_fail(e, "normalize launch");
 }
 
+dvr_status dvr_denoise_workspace(const dvr_grid *grid, int32_t mode, size_t *bytes)
+{
+    dvr_status s = check_grid(grid);
+    if (s) return s;
+    if (!bytes) return fail(DVR_E_NULL, "bytes is NULL");
+    if (mode != DVR_DENOISE_GAUSS && mode != DVR_DENOISE_MEDIAN3) return fail(DVR_E_INVALID_ARG, "unknown denoise mode");
+    *bytes = mode == DVR_DENOISE_GAUSS ? (size_t)8 * (size_t)nvox(grid) : 0;
+    return DVR_OK;
+}
+
+dvr_status dvr_denoise(const void *vol, int32_t dtype, const dvr_grid *grid, int32_t mode, float sigma_mm, void *out,
+                       void *ws, size_t ws_bytes, hipStream_t stream)
+{
+    dvr_status s = check_grid(grid);
+    if (s) return s;
+    if (mode != DVR_DENOISE_GAUSS && mode != DVR_DENOISE_MEDIAN3) return fail(DVR_E_INVALID_ARG, "unknown denoise mode");
+    if (!vol || !out) return fail(DVR_E_NULL, "vol and out must be non-NULL");
+    if (vol == out) return fail(DVR_E_INVALID_ARG, "out must not alias vol");
+    if (!aligned16(vol) || !aligned16(out)) return fail(DVR_E_ALIGN, "vol and out must be 16-byte aligned");
+    if (dtype != DVR_F32 && dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "dtype must be F32 or F16");
+    int r[3] = {0, 0, 0};
+    float w[3][DVR_MAX_RADIUS + 1] = {};
+    if (mode == DVR_DENOISE_GAUSS) {
+        if (!finite_pos(sigma_mm)) return fail(DVR_E_INVALID_ARG, "sigma_mm must be > 0");
+        const double h[3] = {grid->hx, grid->hy, grid->hz};
+        for (int a = 0; a < 3; ++a) {
+            const double sv = sigma_mm / h[a];
+            if (gauss_radius(sv) > DVR_MAX_RADIUS) return fail(DVR_E_INVALID_ARG, "Gaussian radius beyond DVR_MAX_RADIUS");
+            dvr::AxisTaps t;
+            axis_taps(sv, h[a], t);
+            r[a] = t.R - 1;
+            for (int j = 0; j <= r[a]; ++j) w[a][j] = t.G[j];
+        }
+        if (!ws) return fail(DVR_E_WORKSPACE, "workspace is NULL");
+        if (!aligned16(ws)) return fail(DVR_E_ALIGN, "workspace is not 16-byte aligned");
+        if (ws_bytes < (size_t)8 * (size_t)nvox(grid)) return fail(DVR_E_WORKSPACE, "workspace too small");
+    }
+    hipError_t e = dvr::launch_denoise(vol, dtype, *grid, mode, r, w, out, (float *)ws, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "denoise launch");
+}
+
 dvr_status dvr_histogram(const void *vol, int32_t dtype, int64_t n, float floor_, uint32_t *hist, uint32_t *used,
                          hipStream_t stream)
 {

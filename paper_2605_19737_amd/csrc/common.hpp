@@ -103,6 +103,9 @@ hipError_t launch_peaks(const uint32_t *hist, int min_sep, dvr_peaks *out, hipSt
 hipError_t launch_tissue_tf(const dvr_peaks *pk, const dvr_tissue_tf_params &p, float *knots, float *rgba,
                             hipStream_t st);
 
+hipError_t launch_denoise(const void *vol, int dt, const dvr_grid &g, int mode, const int r[3],
+                          const float w[3][DVR_MAX_RADIUS + 1], void *out, float *ws, hipStream_t st);
+
 struct RenderArgs;
 hipError_t launch_render(const RenderArgs &a, hipStream_t st);
 hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st);
