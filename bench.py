@@ -104,10 +104,13 @@ def main():
     cams = [dvr.camera_struct(c) for c in w.cams]
     nvox = vol.numel()
     nz, ny, nx = vol.shape
-    # no brick table here: the head's Rician background leaves few empty 4^3 bricks, and on FP32 planar
-    # features the per-brick lookups cost ~5 % more than the transparent samples they save (the
-    # table pays off where empty space is clean: see the 512x512x400 leg)
-    feats = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float32, bricks=False)
+    # FP32 features in the split layout (I and V planes, one (gx, gy, gz, k) record per voxel): the
+    # same values as planar, half the gathers per shaded corner.  No brick table here: the head's
+    # Rician background leaves few empty 4^3 bricks, and the per-brick lookups cost more than the
+    # transparent samples they save (the table pays off where empty space is clean: see the
+    # 512x512x400 leg)
+    from paper_2605_19737_amd import _abi as abi_
+    feats = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float32, abi_.DVR_SPLIT, bricks=False)
     wsb = dvr.features_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     V = len(cams)
@@ -118,7 +121,7 @@ def main():
     def step(timing=None):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         e0.record(stream)
-        dvr.features(vol, w.spacing, w.sigmas, c=w.c, out=feats, ws=ws)
+        dvr.features(vol, w.spacing, w.sigmas, c=w.c, layout=feats.layout, out=feats, ws=ws)
         e1.record(stream)
         _, T, k = dvr.render(vol, feats, knots, tf, w.params, cams, out=img, counters=counters)
         e2.record(stream)
@@ -163,7 +166,7 @@ def main():
                    "views_per_launch": tr.get("views_per_launch"), "source_sha": sha}
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_render (FP32 planar, K<=8)",
+                "traffic": traffic, "kernel": "k_render (FP32 split layout, K<=8)",
                 "avg_launch_ms": round(1e3 * render_launch_s, 4),
                 "flops_per_launch": flops_per_step / launches_per_step,
                 "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4)}

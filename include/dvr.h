@@ -56,8 +56,13 @@ typedef enum dvr_dtype { DVR_F32 = 0, DVR_F16 = 1, DVR_U16 = 2 } dvr_dtype;
  *   DVR_INTERLEAVED:  grad = one record of 8 values per voxel, [nz][ny][nx][8] =
  *                     (I, gx, gy, gz, kappa, V, 0, 0) of the buffer's dtype (32 B in F32, 16 B in
  *                     F16); kappa and ves are unused.  The record carries the intensity so that the
- *                     raymarcher fetches one record per corner. */
-typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1 } dvr_layout;
+ *                     raymarcher fetches one record per corner.
+ *   DVR_SPLIT:        grad = one record of 4 values per voxel, [nz][ny][nx][4] = (gx, gy, gz, kappa)
+ *                     (16 B in F32, 8 B in F16); ves = [nz][ny][nx]; kappa is unused; the intensity
+ *                     is the volume, as in PLANAR.  A sample of zero extinction fetches only I; a
+ *                     shaded one fetches I, one record and V per corner (the same 24 / 12 bytes per
+ *                     voxel as PLANAR, in half the gathers).  Not supported by the batched launch. */
+typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1, DVR_SPLIT = 2 } dvr_layout;
 
 typedef struct dvr_grid {
     int32_t nx, ny, nz; /* >= 2 each, nx*ny*nz < 2^31 */

@@ -69,7 +69,8 @@ def camera_struct(cam):
 @dataclass
 class Features:
     """Device-resident feature fields.  planar: grad [3][nz][ny][nx], kappa, ves [nz][ny][nx];
-    interleaved: grad [nz][ny][nx][8] = (I, gx, gy, gz, kappa, V, 0, 0); gmax: 1-element tensor."""
+    interleaved: grad [nz][ny][nx][8] = (I, gx, gy, gz, kappa, V, 0, 0); split: grad [nz][ny][nx][4] =
+    (gx, gy, gz, kappa), ves [nz][ny][nx]; gmax: 1-element tensor."""
     grad: torch.Tensor
     kappa: torch.Tensor | None
     ves: torch.Tensor | None
@@ -121,6 +122,10 @@ def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANA
     if layout == abi.DVR_PLANAR:
         grad = torch.empty((3, nz, ny, nx), dtype=dtype, device=device)
         kappa = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+        ves = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+    elif layout == abi.DVR_SPLIT:
+        grad = torch.empty((nz, ny, nx, 4), dtype=dtype, device=device)
+        kappa = None
         ves = torch.empty((nz, ny, nx), dtype=dtype, device=device)
     else:
         grad = torch.empty((nz, ny, nx, 8), dtype=dtype, device=device)

@@ -16,7 +16,7 @@ DVR_OK = 0
 STATUS = {0: "DVR_OK", -1: "DVR_E_INVALID_ARG", -2: "DVR_E_NULL", -3: "DVR_E_ALIGN", -4: "DVR_E_UNSUPPORTED",
           -5: "DVR_E_NOMEM", -6: "DVR_E_DEVICE", -8: "DVR_E_TIMEOUT", -9: "DVR_E_WORKSPACE"}
 DVR_F32, DVR_F16, DVR_U16 = 0, 1, 2
-DVR_PLANAR, DVR_INTERLEAVED = 0, 1
+DVR_PLANAR, DVR_INTERLEAVED, DVR_SPLIT = 0, 1, 2
 DVR_MAX_SIGMA = 8
 DVR_BRICK = 4
 DVR_DENOISE_GAUSS, DVR_DENOISE_MEDIAN3 = 0, 1

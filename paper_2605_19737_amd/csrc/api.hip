@@ -86,8 +86,8 @@ dvr_status check_feat_buf(const dvr_features_buf *f, bool need_writable)
     (void)need_writable;
     if (!f) return fail(DVR_E_NULL, "features buffer is NULL");
     if (f->dtype != DVR_F32 && f->dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "feature dtype must be F32 or F16");
-    if (f->layout != DVR_PLANAR && f->layout != DVR_INTERLEAVED)
-        return fail(DVR_E_UNSUPPORTED, "feature layout must be PLANAR or INTERLEAVED");
+    if (f->layout != DVR_PLANAR && f->layout != DVR_INTERLEAVED && f->layout != DVR_SPLIT)
+        return fail(DVR_E_UNSUPPORTED, "feature layout must be PLANAR, INTERLEAVED or SPLIT");
     if (!f->grad || !f->gmax) return fail(DVR_E_NULL, "features grad/gmax is NULL");
     if (!aligned16(f->grad)) return fail(DVR_E_ALIGN, "features grad is not 16-byte aligned");
     if (((uintptr_t)f->gmax & 3u) != 0) return fail(DVR_E_ALIGN, "gmax is not 4-byte aligned");
@@ -95,11 +95,25 @@ dvr_status check_feat_buf(const dvr_features_buf *f, bool need_writable)
         if (!f->kappa || !f->ves) return fail(DVR_E_NULL, "planar features need kappa and ves");
         if (!aligned16(f->kappa) || !aligned16(f->ves)) return fail(DVR_E_ALIGN, "kappa/ves not 16-byte aligned");
     }
+    if (f->layout == DVR_SPLIT) {
+        if (!f->ves) return fail(DVR_E_NULL, "split features need ves");
+        if (!aligned16(f->ves)) return fail(DVR_E_ALIGN, "ves not 16-byte aligned");
+    }
     if (((uintptr_t)f->bricks & 7u) != 0) return fail(DVR_E_ALIGN, "bricks is not 8-byte aligned");
     return DVR_OK;
 }
 
 int nbricks(int n) { return (n - 1 + DVR_BRICK - 1) / DVR_BRICK; }
+
+// every feature array is addressed with 32-bit byte offsets
+dvr_status check_feat_size(const dvr_grid *g, const dvr_features_buf *f)
+{
+    const uint64_t es = f->dtype == DVR_F32 ? 4u : 2u;
+    const uint64_t per = f->layout == DVR_INTERLEAVED ? 8u * es : (f->layout == DVR_SPLIT ? 4u * es : es);
+    if ((uint64_t)g->nx * (uint64_t)g->ny * (uint64_t)g->nz * per >= ((uint64_t)1 << 32))
+        return fail(DVR_E_INVALID_ARG, "feature arrays of this grid exceed 4 GiB (32-bit offsets)");
+    return DVR_OK;
+}
 
 void axis_taps(double sigma_vox, double h, dvr::AxisTaps &t)
 {
@@ -277,6 +291,7 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
     if (s) return s;
     if ((s = check_fparams(grid, fp))) return s;
     if ((s = check_feat_buf(out, true))) return s;
+    if ((s = check_feat_size(grid, out))) return s;
     if (!vol) return fail(DVR_E_NULL, "vol is NULL");
     if (!aligned16(vol)) return fail(DVR_E_ALIGN, "vol is not 16-byte aligned");
     if (vol_dtype != DVR_F32 && vol_dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "vol dtype must be F32 or F16");
@@ -317,8 +332,9 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
     dvr_status s = check_grid(grid);
     if (s) return s;
     if ((s = check_feat_buf(feat, false))) return s;
-    if (feat->layout == DVR_PLANAR) {
-        if (!vol) return fail(DVR_E_NULL, "vol is NULL (planar features sample it)");
+    if ((s = check_feat_size(grid, feat))) return s;
+    if (feat->layout != DVR_INTERLEAVED) {
+        if (!vol) return fail(DVR_E_NULL, "vol is NULL (planar and split features sample it)");
         if (!aligned16(vol)) return fail(DVR_E_ALIGN, "vol is not 16-byte aligned");
         if (vol_dtype != feat->dtype) return fail(DVR_E_UNSUPPORTED, "planar render needs vol dtype == feature dtype");
     }

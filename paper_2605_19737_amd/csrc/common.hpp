@@ -43,6 +43,7 @@ __device__ __forceinline__ float ldh(Buf b, uint32_t byte_off)
 typedef uint32_t u32x4 __attribute__((ext_vector_type(4)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
+typedef _Float16 f16x4 __attribute__((ext_vector_type(4)));
 __device__ __forceinline__ u32x4 ld4(Buf b, uint32_t byte_off)
 {
     return __builtin_amdgcn_raw_buffer_load_b128(b.r, byte_off, 0, 0);

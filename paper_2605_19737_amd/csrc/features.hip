@@ -249,6 +249,10 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
             return launch_xy_r<DVR_F32, DVR_F32, DVR_PLANAR, kRFastMin>(a, taps, st);
         if (vol_dt == DVR_F16 && odt == DVR_F16 && lay == DVR_INTERLEAVED)
             return launch_xy_r<DVR_F16, DVR_F16, DVR_INTERLEAVED, kRFastMin>(a, taps, st);
+        if (vol_dt == DVR_F32 && odt == DVR_F32 && lay == DVR_SPLIT)
+            return launch_xy_r<DVR_F32, DVR_F32, DVR_SPLIT, kRFastMin>(a, taps, st);
+        if (vol_dt == DVR_F16 && odt == DVR_F16 && lay == DVR_SPLIT)
+            return launch_xy_r<DVR_F16, DVR_F16, DVR_SPLIT, kRFastMin>(a, taps, st);
     }
 #define DVR_XY(D, O, L) \
     if (vol_dt == D && odt == O && lay == L) return launch_xy<D, O, L>(a, taps, st);
@@ -260,6 +264,10 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
     DVR_XY(DVR_F16, DVR_F32, DVR_INTERLEAVED)
     DVR_XY(DVR_F16, DVR_F16, DVR_PLANAR)
     DVR_XY(DVR_F16, DVR_F16, DVR_INTERLEAVED)
+    DVR_XY(DVR_F32, DVR_F32, DVR_SPLIT)
+    DVR_XY(DVR_F32, DVR_F16, DVR_SPLIT)
+    DVR_XY(DVR_F16, DVR_F32, DVR_SPLIT)
+    DVR_XY(DVR_F16, DVR_F16, DVR_SPLIT)
 #undef DVR_XY
     return hipErrorInvalidValue;
 }

@@ -281,6 +281,19 @@ __device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const f
             st<OUT_DT>(a.kappa, v, kap);
         }
         st<OUT_DT>(a.ves, v, V);
+    } else if constexpr (LAYOUT == DVR_SPLIT) {
+        if (!a.first) V = fmaxf(V, ldo<OUT_DT>(a.ves, v));
+        else if constexpr (OUT_DT == DVR_F32) {
+            reinterpret_cast<float4 *>(a.grad)[v] = make_float4(gx_, gy_, gz_, kap);
+        } else {
+            union { __half h[4]; uint2 u; } rec;
+            rec.h[0] = __float2half_rn(gx_);
+            rec.h[1] = __float2half_rn(gy_);
+            rec.h[2] = __float2half_rn(gz_);
+            rec.h[3] = __float2half_rn(kap);
+            reinterpret_cast<uint2 *>(a.grad)[v] = rec.u;
+        }
+        st<OUT_DT>(a.ves, v, V);
     } else {
         if (!a.first) {
             V = fmaxf(V, ldo<OUT_DT>(a.grad, 8u * v + 5u));

@@ -167,11 +167,12 @@ __device__ __forceinline__ bool brick_empty(const TFShared<KMAX> &sh, const floa
 }
 
 // ------------------------------------------------------------------------------------------------
-// Feature fetch.  LAYOUT/DT select planar planes or interleaved records.
+// Feature fetch.  LAYOUT/DT select planar planes, interleaved records, or the split layout (I and V
+// planes plus a (gx, gy, gz, k) record, addressed at 4x the plane offsets).
 template <int LAYOUT, int DT>
 struct Vox {
-    Buf b[6];  // planar: I, gx, gy, gz, kappa, V;  interleaved: b[0] = records
-    uint32_t sx, sy, sz;  // byte strides of +1 in x, y, z
+    Buf b[6];  // planar: I, gx, gy, gz, kappa, V;  interleaved: b[0] = records;  split: I, records, V
+    uint32_t sx, sy, sz;  // byte strides of +1 in x, y, z (split: in the planes)
 
     __device__ __forceinline__ void init(const KFeat &f, const KGrid &g)
     {
@@ -186,6 +187,11 @@ struct Vox {
             b[3] = make_buf(gp + (size_t)2 * N * es, N * es);
             b[4] = make_buf(f.kappa, N * es);
             b[5] = make_buf(f.ves, N * es);
+        } else if constexpr (LAYOUT == DVR_SPLIT) {
+            es = ElemSize<DT>::v;
+            b[0] = make_buf(f.vol, N * es);
+            b[1] = make_buf(f.grad, N * 4u * es);
+            b[2] = make_buf(f.ves, N * es);
         } else {
             es = (DT == DVR_F32) ? 32u : 16u;
             b[0] = make_buf(f.grad, N * es);
@@ -252,7 +258,7 @@ struct CornerCache {
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
-            if constexpr (LAYOUT == DVR_PLANAR) {
+            if constexpr (LAYOUT != DVR_INTERLEAVED) {
                 if constexpr (DT == DVR_F32) v[e][0] = ldf(vx.b[0], off);
                 else v[e][0] = ldh(vx.b[0], off);
             } else if constexpr (DT == DVR_F32) {
@@ -288,6 +294,28 @@ struct CornerCache {
                 for (int ch = 1; ch < 6; ++ch) {
                     if constexpr (DT == DVR_F32) v[e][ch] = ldf(vx.b[ch], off);
                     else v[e][ch] = ldh(vx.b[ch], off);
+                }
+            }
+        } else if constexpr (LAYOUT == DVR_SPLIT) {
+            if (feat) return;
+            feat = true;
+#pragma unroll
+            for (int e = 0; e < 8; ++e) {
+                const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
+                if constexpr (DT == DVR_F32) {
+                    const f32x4 r = __builtin_bit_cast(f32x4, ld4(vx.b[1], off << 2));
+                    v[e][1] = r.x;
+                    v[e][2] = r.y;
+                    v[e][3] = r.z;
+                    v[e][4] = r.w;
+                    v[e][5] = ldf(vx.b[2], off);
+                } else {
+                    const f16x4 r = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(vx.b[1].r, off << 2, 0, 0));
+                    v[e][1] = (float)r.x;
+                    v[e][2] = (float)r.y;
+                    v[e][3] = (float)r.z;
+                    v[e][4] = (float)r.w;
+                    v[e][5] = ldh(vx.b[2], off);
                 }
             }
         }
@@ -652,7 +680,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
     const bool at_last = (kl == r.N - 1);
     for (int a = 0; a < 3; ++a) q[a] = (kl < 0) ? 0 : (at_last ? r.ql[a] : r.q0[a] + (int64_t)kl * r.dq[a]);
     // byte offset of a corner -> voxel index (element sizes are powers of two)
-    const uint32_t esh = (LAYOUT == DVR_PLANAR) ? (DT == DVR_F32 ? 2u : 1u) : (DT == DVR_F32 ? 5u : 4u);
+    const uint32_t esh = (LAYOUT != DVR_INTERLEAVED) ? (DT == DVR_F32 ? 2u : 1u) : (DT == DVR_F32 ? 5u : 4u);
     SegAcc<tf_copies(KMAX)> sa;
     sa.seg = -2;
     for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;

@@ -40,6 +40,12 @@ def feats_np(f: dvr.Features):
         k = f.kappa.float().cpu().numpy().astype(np.float64)
         V = f.ves.float().cpu().numpy().astype(np.float64)
         I = None
+    elif f.layout == abi.DVR_SPLIT:
+        rec = f.grad.float().cpu().numpy().astype(np.float64)
+        g = np.moveaxis(rec[..., 0:3], -1, 0)
+        k = rec[..., 3]
+        V = f.ves.float().cpu().numpy().astype(np.float64)
+        I = None
     else:
         rec = f.grad.float().cpu().numpy().astype(np.float64)
         g = np.moveaxis(rec[..., 1:4], -1, 0)
