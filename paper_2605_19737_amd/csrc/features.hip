@@ -123,39 +123,33 @@ static hipError_t launch_xy_r(const XYArgs &a, const ScaleTaps &taps, hipStream_
     }
 }
 
-// Brick table: one wave per brick; lanes cover the brick's (x, y) voxel columns and walk z, then a
-// wave min/max.  SRC: 0 F32 volume, 1 F16 volume, 2 F32 records (I at stride 8), 3 F16 records.
+// Brick table: one lane per brick (consecutive lanes on consecutive bricks along x), each reading its
+// (DVR_BRICK + 1)^3 voxels.  SRC: 0 F32 volume, 1 F16 volume, 2 F32 records (I at stride 8), 3 F16
+// records.
 template <int SRC>
 __global__ __launch_bounds__(256) void k_bricks(const void *__restrict__ src, float2 *__restrict__ out, int nx, int ny,
                                                 int nz, int nbx, int nby, int nbz)
 {
-    const int wv = (int)(blockIdx.x * 4u + (threadIdx.x >> 6));
-    const int lane = threadIdx.x & 63;
-    if (wv >= nbx * nby * nbz) return;  // the whole wave leaves together
-    const int bx = wv % nbx, by = (wv / nbx) % nby, bz = wv / (nbx * nby);
+    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= nbx * nby * nbz) return;
+    const int bx = i % nbx, by = (i / nbx) % nby, bz = i / (nbx * nby);
     const int x0 = bx * DVR_BRICK, y0 = by * DVR_BRICK, z0 = bz * DVR_BRICK;
     const int x1 = min(x0 + DVR_BRICK, nx - 1), y1 = min(y0 + DVR_BRICK, ny - 1), z1 = min(z0 + DVR_BRICK, nz - 1);
-    const int wx = x1 - x0 + 1, wy = y1 - y0 + 1;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     float mn = INFINITY, mx = -INFINITY;
-    for (int i = lane; i < wx * wy; i += 64) {
-        const int x = x0 + i % wx, y = y0 + i / wx;
-        for (int z = z0; z <= z1; ++z) {
-            const uint32_t v = (uint32_t)z * plane + (uint32_t)y * nx + x;
-            float f;
-            if constexpr (SRC == 0) f = reinterpret_cast<const float *>(src)[v];
-            else if constexpr (SRC == 1) f = __half2float(reinterpret_cast<const __half *>(src)[v]);
-            else if constexpr (SRC == 2) f = reinterpret_cast<const float *>(src)[8u * v];
-            else f = __half2float(reinterpret_cast<const __half *>(src)[8u * v]);
-            mn = fminf(mn, f);
-            mx = fmaxf(mx, f);
-        }
-    }
-    for (int o = 32; o > 0; o >>= 1) {
-        mn = fminf(mn, __shfl_xor(mn, o, 64));
-        mx = fmaxf(mx, __shfl_xor(mx, o, 64));
-    }
-    if (lane == 0) out[wv] = make_float2(mn, mx);
+    for (int z = z0; z <= z1; ++z)
+        for (int y = y0; y <= y1; ++y)
+            for (int x = x0; x <= x1; ++x) {
+                const uint32_t v = (uint32_t)z * plane + (uint32_t)y * nx + x;
+                float f;
+                if constexpr (SRC == 0) f = reinterpret_cast<const float *>(src)[v];
+                else if constexpr (SRC == 1) f = __half2float(reinterpret_cast<const __half *>(src)[v]);
+                else if constexpr (SRC == 2) f = reinterpret_cast<const float *>(src)[8u * v];
+                else f = __half2float(reinterpret_cast<const __half *>(src)[8u * v]);
+                mn = fminf(mn, f);
+                mx = fmaxf(mx, f);
+            }
+    out[i] = make_float2(mn, mx);
 }
 
 hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const dvr_features_buf &out, hipStream_t st)
@@ -163,9 +157,10 @@ hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const d
     const int nbx = (g.nx - 1 + DVR_BRICK - 1) / DVR_BRICK, nby = (g.ny - 1 + DVR_BRICK - 1) / DVR_BRICK,
               nbz = (g.nz - 1 + DVR_BRICK - 1) / DVR_BRICK;
     const int nb = nbx * nby * nbz;
-    dim3 grid((nb + 3) / 4);
+    dim3 grid((nb + 255) / 256);
     float2 *o = reinterpret_cast<float2 *>(out.bricks);
-    if (out.layout == DVR_INTERLEAVED) {
+    // the records' I is the volume itself when the dtypes agree (read the contiguous volume then)
+    if (out.layout == DVR_INTERLEAVED && out.dtype != vol_dt) {
         if (out.dtype == DVR_F32)
             hipLaunchKernelGGL(k_bricks<2>, grid, dim3(256), 0, st, out.grad, o, g.nx, g.ny, g.nz, nbx, nby, nbz);
         else
