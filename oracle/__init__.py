@@ -59,7 +59,7 @@ def lib():
         L.oracle_render.argtypes = [dp, dp, dp, dp, i, i, i, d, d, d, d, i, dp, dp, dp, dp, i, ip, i64,
                                     dp, dp, ip, i64p]
         L.oracle_render_vjp.argtypes = [dp, dp, dp, dp, i, i, i, d, d, d, d, i, dp, dp, dp, dp, i, ip, i64,
-                                        dp, dp, dp]
+                                        dp, dp, dp, dp, dp, dp, dp]
         _lib = L
     return _lib
 
@@ -208,8 +208,11 @@ def render(vol, feats, gmax, spacing, knots, rgba, params, cams, pix=None):
     return dict(rgba=out, T_last=T, k_last=k, nsamp=ns.value)
 
 
-def render_vjp(vol, feats, gmax, spacing, knots, rgba, params, cams, dout, pix=None, want_dI=True):
-    """dL/d(TF values) [K][4] and dL/dI [nz][ny][nx] for upstream dout (same layout as render)."""
+def render_vjp(vol, feats, gmax, spacing, knots, rgba, params, cams, dout, pix=None, want_dI=True,
+               want_features=False):
+    """dL/d(TF values) [K][4] and dL/dI [nz][ny][nx] for upstream dout (same layout as render).
+    want_features: also dict(g [3][nz][ny][nx], kappa, V, gmax) of dL/d(feature values), returned
+    as a third element."""
     camarr = pack_cams(cams)
     pix = all_pixels(cams) if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
     d = _f64(dout).reshape(-1, 4)
@@ -217,9 +220,16 @@ def render_vjp(vol, feats, gmax, spacing, knots, rgba, params, cams, dout, pix=N
     keep, args = _scene_args(vol, feats, gmax, spacing, knots, rgba, params)
     K = len(keep[4])
     dtf = np.empty((K, 4))
-    dI = np.empty(keep[0].shape) if want_dI else None
+    shape = keep[0].shape
+    dI = np.empty(shape) if want_dI else None
+    fg = dict(g=np.empty((3,) + shape), kappa=np.empty(shape), V=np.empty(shape)) if want_features else None
+    dgm = C.c_double()
     rc = lib().oracle_render_vjp(*args, _p(camarr), len(camarr), _p(pix, C.c_int32), len(pix), _p(d),
-                                 _p(dtf), _p(dI))
+                                 _p(dtf), _p(dI), _p(fg["g"]) if fg else None, _p(fg["kappa"]) if fg else None,
+                                 _p(fg["V"]) if fg else None, C.byref(dgm) if fg else None)
     assert rc == 0
     del keep
+    if fg is not None:
+        fg["gmax"] = dgm.value
+        return dtf, dI, fg
     return dtf, dI

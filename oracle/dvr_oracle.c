@@ -406,7 +406,12 @@ static int tf_eval(const scene_t *sc, double I, double v[4], double dv[4], doubl
 /* One sample's optical state (Eq. 4 with the extinction reading): sigma_s = tau * m * w * u,   */
 /* m = (1-lg) + lg min(|g|/gmax, 1), w = (1-lk) + lk |k| / (|k| + k0), u = 1 + lv V,            */
 /* x = sigma_s delta_k, alpha = 1 - exp(-x).                                                     */
-typedef struct { double alpha, x, M, dk, T, c[3], v[4], dv[4], t; int seg; corners_t cn; } samp_t;
+typedef struct {
+    double alpha, x, M, dk, T, c[3], v[4], dv[4], t;
+    double gv[3], gn, kap, m, w, u; /* interpolated features and the three factors of M */
+    int seg;
+    corners_t cn;
+} samp_t;
 
 static void shade(const scene_t *sc, const double p[3], double dk, samp_t *s, int want_corners)
 {
@@ -419,6 +424,8 @@ static void shade(const scene_t *sc, const double p[3], double dk, samp_t *s, in
     const double w = (1.0 - sc->lk) + sc->lk * ak / (ak + sc->k0);
     const double u = 1.0 + sc->lv * ves;
     s->M = m * w * u;
+    s->m = m; s->w = w; s->u = u;
+    s->gv[0] = gv[0]; s->gv[1] = gv[1]; s->gv[2] = gv[2]; s->gn = gn; s->kap = kap;
     s->dk = dk;
     s->x = s->v[3] * s->M * dk;
     s->alpha = -expm1(-s->x);
@@ -496,15 +503,18 @@ int oracle_render(const double *I, const double *g, const double *kap, const dou
 }
 
 /* Reverse mode (vector-Jacobian product) of oracle_render with respect to the TF values          */
-/* (R,G,B,tau at each knot) and the voxel intensities, holding gradient, k and V constant.        */
+/* (R,G,B,tau at each knot), the voxel intensities through the TF lookup, and (nullable outputs)  */
+/* the feature values: dL_dg [3][N], dL_dkap [N], dL_dves [N] and dL_dgmax [1].                   */
 /* dout [npix][4] = dL/d(out).  Every sample of a ray is stored, then swept back to front with    */
-/* the plain adjoints of C += T a c and T' = T exp(-x).  dL_dtf [K][4] and dL_dI [N] (nullable)    */
-/* are overwritten.                                                                               */
+/* the plain adjoints of C += T a c and T' = T exp(-x); x = tau M delta with M = m w u gives      */
+/* dL/dM = dL/dx tau delta, and the chain rule through m (|g| / gmax, inactive where clamped at 1),*/
+/* w (|k| / (|k| + k0), derivative 0 at k = 0) and u (1 + lambda_v V).  All outputs overwritten.   */
 int oracle_render_vjp(const double *I, const double *g, const double *kap, const double *ves,
                       int nx, int ny, int nz, double hx, double hy, double hz, double gmax,
                       int K, const double *knots, const double *rgba, const double *prm,
                       const double *cams, int ncam, const int32_t *pix, int64_t npix,
-                      const double *dout, double *dL_dtf, double *dL_dI)
+                      const double *dout, double *dL_dtf, double *dL_dI,
+                      double *dL_dg, double *dL_dkap, double *dL_dves, double *dL_dgmax)
 {
     if (nx < 2 || ny < 2 || nz < 2 || K < 2) return -1;
     scene_t sc;
@@ -512,8 +522,13 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
     const int64_t N = (int64_t)nx * ny * nz;
     for (int e = 0; e < 4 * K; ++e) dL_dtf[e] = 0.0;
     if (dL_dI) for (int64_t v = 0; v < N; ++v) dL_dI[v] = 0.0;
+    if (dL_dg) for (int64_t v = 0; v < 3 * N; ++v) dL_dg[v] = 0.0;
+    if (dL_dkap) for (int64_t v = 0; v < N; ++v) dL_dkap[v] = 0.0;
+    if (dL_dves) for (int64_t v = 0; v < N; ++v) dL_dves[v] = 0.0;
+    double gmax_acc = 0.0;
+    const int want_feat = dL_dg || dL_dkap || dL_dves || dL_dgmax;
     int err = 0;
-#pragma omp parallel
+#pragma omp parallel reduction(+ : gmax_acc)
     {
         double *tfacc = (double *)calloc(4 * K, sizeof(double));
         int64_t cap = 0;
@@ -554,6 +569,38 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
                         tfacc[4 * (s->seg + 1) + ch] += s->t * vbar[ch];
                     }
                 }
+                if (want_feat) {
+                    /* x = tau M dk */
+                    const double Mbar = xbar * s->v[3] * s->dk;
+                    double gvb[3] = {0.0, 0.0, 0.0}, gmb = 0.0;
+                    if (sc.gmax > 0.0 && s->gn > 0.0 && s->gn < sc.gmax) {
+                        const double mb = Mbar * s->w * s->u;
+                        for (int a = 0; a < 3; ++a) gvb[a] = mb * sc.lg * s->gv[a] / (s->gn * sc.gmax);
+                        gmb = -mb * sc.lg * s->gn / (sc.gmax * sc.gmax);
+                    }
+                    const double ak = fabs(s->kap);
+                    const double sg = s->kap > 0.0 ? 1.0 : (s->kap < 0.0 ? -1.0 : 0.0);
+                    const double kb = Mbar * s->m * s->u * sc.lk * sc.k0 * sg / ((ak + sc.k0) * (ak + sc.k0));
+                    const double vb = Mbar * s->m * s->w * sc.lv;
+                    gmax_acc += gmb;
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        const int64_t v = s->cn.idx[c8];
+                        const double wc = s->cn.w[c8];
+                        if (dL_dg)
+                            for (int a = 0; a < 3; ++a) {
+#pragma omp atomic
+                                dL_dg[a * N + v] += wc * gvb[a];
+                            }
+                        if (dL_dkap) {
+#pragma omp atomic
+                            dL_dkap[v] += wc * kb;
+                        }
+                        if (dL_dves) {
+#pragma omp atomic
+                            dL_dves[v] += wc * vb;
+                        }
+                    }
+                }
                 if (dL_dI) {
                     double Ibar = 0.0;
                     for (int ch = 0; ch < 4; ++ch) Ibar += vbar[ch] * s->dv[ch];
@@ -570,5 +617,6 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
         free(tfacc);
         free(buf);
     }
+    if (dL_dgmax) *dL_dgmax = gmax_acc;
     return err;
 }
