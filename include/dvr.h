@@ -247,6 +247,51 @@ dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_gri
                                const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
                                const float *dL_drgba, float *dL_dtf, float *dL_dvol, hipStream_t stream);
 
+/* Gradients with respect to the feature values (dense FP32 in [nz][ny][nx] order whatever the
+ * feature layout), for the feature-pass adjoint: dfeat = device [5][nz][ny][nx] holding
+ * dL/d(gx, gy, gz, k, V); dgmax = device [1] holding dL/d|g|_max. */
+typedef struct dvr_feature_grads {
+    float *dfeat;
+    float *dgmax;
+} dvr_feature_grads;
+
+/* dvr_render_backward plus the gradients with respect to the feature values that Eq. 4 reads
+ * (Sec. 2.4): sigma = tau m w u with m = (1 - lambda_g) + lambda_g min(|g| / |g|_max, 1),
+ * w = (1 - lambda_k) + lambda_k |k| / (|k| + kappa0), u = 1 + lambda_v V; through the trilinear
+ * interpolation to each voxel's g, k and V, and to |g|_max.  Where min(., 1) is at 1 the m term
+ * has no gradient, and w has none at k = 0.  fg: required, both arrays overwritten (FP32 atomics:
+ * the summation order, and so the last bits, vary from run to run).  The other arguments and
+ * outputs are those of dvr_render_backward. */
+dvr_status dvr_render_backward_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                                        const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
+                                        const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
+                                        const float *dL_drgba, float *dL_dtf, float *dL_dvol,
+                                        const dvr_feature_grads *fg, hipStream_t stream);
+
+/* Workspace of dvr_features_backward in bytes (about 81 bytes per voxel plus the band tables). */
+dvr_status dvr_features_backward_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes);
+
+/* Adjoint of dvr_features: adds to dL_dvol the gradient with respect to the voxel intensities I of
+ *   sum_v dL/dg(v) . g(v) + dL/dk(v) k(v) + dL/dV(v) V(v) + dL/d|g|_max |g|_max,
+ * with g the clamped central difference of I (Sec. 2.3 Eq. 2), k = g^T H g / g^T g at the first
+ * scale (Sec. 2.3 Eq. 3, 0 where g = 0), V the maximum over the scales of Frangi's bright-tube
+ * vesselness of sigma^2 H (Sec. 1), H the Hessian of the Gaussian-smoothed volume, all as
+ * dvr_features defines them; fg holds the upstream gradients (the output of
+ * dvr_render_backward_features).  Conventions where the forward is not differentiable: V is
+ * differentiated at the first scale reaching the maximum (FP64 comparison), and not where V = 0;
+ * |g|_max at the voxel of largest |g| (the lowest index on a tie of the FP32-rounded norms); k not
+ * at g = 0; the eigenvalue derivative assumes distinct eigenvalues.  The local derivatives are
+ * evaluated in FP64 (Jacobi eigenvectors), the transposed filters in FP32.
+ * vol: device [nz][ny][nx] F32 or F16 (16-byte aligned), the volume the features were computed
+ * from; fp: as for dvr_features, with c > 0 (the adjoint does not differentiate the automatic c);
+ * dL_dvol: device [nz][ny][nx] float, ACCUMULATED into (add the TF-lookup part from
+ * dvr_render_backward first); ws: device, 256-byte aligned, at least
+ * dvr_features_backward_workspace bytes.  Stream-ordered; nothing is enqueued on a
+ * validation error. */
+dvr_status dvr_features_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                                 const dvr_feature_params *fp, const dvr_feature_grads *fg, float *dL_dvol, void *ws,
+                                 size_t ws_bytes, hipStream_t stream);
+
 /* ---------------------------------------------------------------------------------------------
  * Batched launch: the feature pass of many volumes (uneven shapes, anisotropic spacing) and the
  * raymarch of many views of them, in one persistent kernel recorded in a HIP graph.  The kernel

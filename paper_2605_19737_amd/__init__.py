@@ -204,8 +204,11 @@ def render(vol, feats: Features, knots, rgba, params, cams, want_state=True, out
     return img, T_last, k_last
 
 
-def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_last, dout, want_dvol=True):
-    """dvr_render_backward: returns (dL/dTF [K][4], dL/dvol [nz][ny][nx] or None)."""
+def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_last, dout, want_dvol=True,
+                    want_features=False):
+    """dvr_render_backward: returns (dL/dTF [K][4], dL/dvol [nz][ny][nx] or None); with want_features
+    (dvr_render_backward_features) also dict(g [3][nz][ny][nx], kappa, V, gmax [1]) of the gradients
+    with respect to the feature values."""
     carr = _cams(cams)
     dev = feats.grad.device
     dtf = torch.empty((knots.numel(), 4), dtype=torch.float32, device=dev)
@@ -216,10 +219,40 @@ def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_l
     tf = _tf_struct(knots, rgba)
     rp = _rparams(params)
     st = abi.RayState(T_last.data_ptr(), k_last.data_ptr(), None)
-    abi.check(lib().dvr_render_backward(_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g),
-                                        C.byref(fb), C.byref(tf), C.byref(rp), carr, len(cams), C.byref(st),
-                                        _ptr(dout), _ptr(dtf), _ptr(dvol), _stream()))
-    return dtf, dvol
+    args = (_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g), C.byref(fb), C.byref(tf),
+            C.byref(rp), carr, len(cams), C.byref(st), _ptr(dout), _ptr(dtf), _ptr(dvol))
+    if not want_features:
+        abi.check(lib().dvr_render_backward(*args, _stream()))
+        return dtf, dvol
+    dfeat = torch.empty((5,) + tuple(feats.shape), dtype=torch.float32, device=dev)
+    dgmax = torch.empty(1, dtype=torch.float32, device=dev)
+    fg = abi.FeatureGrads(dfeat.data_ptr(), dgmax.data_ptr())
+    abi.check(lib().dvr_render_backward_features(*args, C.byref(fg), _stream()))
+    return dtf, dvol, dict(g=dfeat[:3], kappa=dfeat[3], V=dfeat[4], gmax=dgmax, packed=dfeat)
+
+
+def features_backward(vol, spacing, sigmas, fgrads, dvol=None, alpha=0.5, beta=0.5, c=0.1, ws=None):
+    """dvr_features_backward: adds dL/dI of the feature pass for the upstream fgrads (the dict that
+    render_backward(..., want_features=True) returns, or g [3][...], kappa, V, gmax [1] tensors) to
+    dvol (zeros when None) and returns dvol."""
+    _require_cuda(vol)
+    g = grid_struct(vol.shape, spacing)
+    fp = _fparams(sigmas, alpha, beta, c, 0.0)
+    packed = fgrads.get("packed")
+    if packed is None:
+        packed = torch.cat([fgrads["g"].reshape(3, -1), fgrads["kappa"].reshape(1, -1),
+                            fgrads["V"].reshape(1, -1)]).float().contiguous()
+    dgmax = fgrads["gmax"].reshape(1).float().contiguous()
+    if dvol is None:
+        dvol = torch.zeros(vol.shape, dtype=torch.float32, device=vol.device)
+    n = C.c_size_t()
+    abi.check(lib().dvr_features_backward_workspace(C.byref(g), C.byref(fp), C.byref(n)))
+    if ws is None or ws.numel() < n.value:
+        ws = torch.empty(n.value, dtype=torch.uint8, device=vol.device)
+    fg = abi.FeatureGrads(packed.data_ptr(), dgmax.data_ptr())
+    abi.check(lib().dvr_features_backward(_ptr(vol), _dt(vol), C.byref(g), C.byref(fp), C.byref(fg), _ptr(dvol),
+                                          _ptr(ws), n.value, _stream()))
+    return dvol
 
 
 def normalize(raw, out_dtype=torch.float16):

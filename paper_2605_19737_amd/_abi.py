@@ -63,6 +63,10 @@ class RayState(C.Structure):
     _fields_ = [("T_last", C.c_void_p), ("k_last", C.c_void_p), ("counters", C.c_void_p)]
 
 
+class FeatureGrads(C.Structure):
+    _fields_ = [("dfeat", C.c_void_p), ("dgmax", C.c_void_p)]
+
+
 class BatchVolume(C.Structure):
     _fields_ = [("vol", C.c_void_p), ("vol_dtype", C.c_int32), ("grid", Grid), ("feat", FeaturesBuf)]
 
@@ -119,13 +123,18 @@ def load():
                              P(RayState), vp]
     L.dvr_render_backward.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32,
                                       P(RayState), vp, vp, vp, vp]
+    L.dvr_render_backward_features.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera),
+                                               i32, P(RayState), vp, vp, vp, P(FeatureGrads), vp]
+    L.dvr_features_backward_workspace.argtypes = [P(Grid), P(FeatureParams), P(sz)]
+    L.dvr_features_backward.argtypes = [vp, i32, P(Grid), P(FeatureParams), P(FeatureGrads), vp, vp, sz, vp]
     L.dvr_batch_create.argtypes = [P(BatchDesc), P(vp)]
     L.dvr_batch_launch.argtypes = [vp, vp]
     L.dvr_batch_check.argtypes = [vp, vp]
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
     for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_denoise_workspace", "dvr_denoise", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
-                 "dvr_render", "dvr_render_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
+                 "dvr_render", "dvr_render_backward", "dvr_render_backward_features", "dvr_features_backward_workspace",
+                 "dvr_features_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32
     _lib = L

@@ -10,7 +10,8 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "libdvr.so")
-SOURCES = ["api.hip", "batch.hip", "features.hip", "normalize.hip", "render.hip", "tissue.hip", "denoise.hip"]
+SOURCES = ["api.hip", "batch.hip", "features.hip", "features_bwd.hip", "normalize.hip", "render.hip", "tissue.hip",
+           "denoise.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 
 FLAGS = [

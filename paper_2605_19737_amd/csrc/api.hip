@@ -323,6 +323,63 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
     return DVR_OK;
 }
 
+static dvr_status feat_bwd_plan(const dvr_grid *grid, const dvr_feature_params *fp, dvr::FeatBwdPlan &p)
+{
+    dvr_status s = check_grid(grid);
+    if (s) return s;
+    if ((s = check_fparams(grid, fp))) return s;
+    if (!(fp->c > 0.f)) return fail(DVR_E_INVALID_ARG, "the feature adjoint needs Frangi's c > 0 (got %g)", (double)fp->c);
+    const double h[3] = {grid->hx, grid->hy, grid->hz};
+    memset(&p, 0, sizeof p);
+    p.nsigma = fp->nsigma;
+    for (int sc = 0; sc < fp->nsigma; ++sc) {
+        const double sg = fp->sigma_mm[sc];
+        for (int a = 0; a < 3; ++a) axis_taps(sg / h[a], h[a], p.taps[sc].ax[a]);
+        p.taps[sc].sigma2 = (float)(sg * sg);
+        p.sigma2[sc] = sg * sg;
+    }
+    const double al = fp->alpha, be = fp->beta, c = fp->c;
+    p.inv2a2 = 1.0 / (2.0 * al * al);
+    p.inv2b2 = 1.0 / (2.0 * be * be);
+    p.inv2c2 = 1.0 / (2.0 * c * c);
+    for (int a = 0; a < 3; ++a) p.inv2h[a] = 1.0 / (2.0 * h[a]);
+    return DVR_OK;
+}
+
+dvr_status dvr_features_backward_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes)
+{
+    dvr::FeatBwdPlan p;
+    dvr_status s = feat_bwd_plan(grid, fp, p);
+    if (s) return s;
+    if (!bytes) return fail(DVR_E_NULL, "bytes is NULL");
+    *bytes = dvr::features_bwd_ws_bytes(*grid, p);
+    return DVR_OK;
+}
+
+dvr_status dvr_features_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                                 const dvr_feature_params *fp, const dvr_feature_grads *fg, float *dL_dvol, void *ws,
+                                 size_t ws_bytes, hipStream_t stream)
+{
+    dvr::FeatBwdPlan p;
+    dvr_status s = feat_bwd_plan(grid, fp, p);
+    if (s) return s;
+    if (!vol) return fail(DVR_E_NULL, "vol is NULL");
+    if (!aligned16(vol)) return fail(DVR_E_ALIGN, "vol is not 16-byte aligned");
+    if (vol_dtype != DVR_F32 && vol_dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "vol dtype must be F32 or F16");
+    if (!fg || !fg->dfeat || !fg->dgmax) return fail(DVR_E_NULL, "feature gradients are required");
+    if (((uintptr_t)fg->dfeat & 3u) || ((uintptr_t)fg->dgmax & 3u))
+        return fail(DVR_E_ALIGN, "feature gradient buffers misaligned");
+    if (!dL_dvol) return fail(DVR_E_NULL, "dL_dvol is NULL");
+    if ((uintptr_t)dL_dvol & 3u) return fail(DVR_E_ALIGN, "dL_dvol is not 4-byte aligned");
+    const size_t need = dvr::features_bwd_ws_bytes(*grid, p);
+    if (!ws) return fail(DVR_E_WORKSPACE, "workspace is NULL");
+    if (((uintptr_t)ws & 255u)) return fail(DVR_E_ALIGN, "workspace is not 256-byte aligned");
+    if (ws_bytes < need)
+        return fail(DVR_E_WORKSPACE, "workspace of %zu bytes is smaller than the required %zu", ws_bytes, need);
+    hipError_t e = dvr::launch_features_backward(vol, vol_dtype, *grid, p, fg->dfeat, fg->dgmax, dL_dvol, ws, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "feature adjoint launch");
+}
+
 }  // extern "C"
 
 dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
@@ -438,10 +495,11 @@ dvr_status dvr_render(const void *vol, int32_t vol_dtype, const dvr_grid *grid, 
     return e == hipSuccess ? DVR_OK : dev_fail(e, "render launch");
 }
 
-dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
-                               const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
-                               const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
-                               const float *dL_drgba, float *dL_dtf, float *dL_dvol, hipStream_t stream)
+static dvr_status render_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                                  const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
+                                  const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
+                                  const float *dL_drgba, float *dL_dtf, float *dL_dvol, const dvr_feature_grads *fg,
+                                  hipStream_t stream)
 {
     if (ncam > 1 << 20) return fail(DVR_E_INVALID_ARG, "too many cameras");
     dvr::KCam *kc = ncam > 0 ? new (std::nothrow) dvr::KCam[ncam] : nullptr;
@@ -452,6 +510,9 @@ dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_gri
     if (s == DVR_OK && (!dL_drgba || !dL_dtf)) s = fail(DVR_E_NULL, "dL_drgba and dL_dtf are required");
     if (s == DVR_OK && (!aligned16(dL_drgba) || ((uintptr_t)dL_dtf & 3u) || (dL_dvol && ((uintptr_t)dL_dvol & 3u))))
         s = fail(DVR_E_ALIGN, "gradient buffers misaligned");
+    if (s == DVR_OK && fg && (!fg->dfeat || !fg->dgmax)) s = fail(DVR_E_NULL, "dfeat and dgmax are required");
+    if (s == DVR_OK && fg && (((uintptr_t)fg->dfeat & 3u) || ((uintptr_t)fg->dgmax & 3u)))
+        s = fail(DVR_E_ALIGN, "feature gradient buffers misaligned");
     if (s != DVR_OK) {
         delete[] kc;
         return s;
@@ -461,11 +522,35 @@ dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_gri
     a.launch.dout = dL_drgba;
     a.launch.dtf = dL_dtf;
     a.launch.dvol = dL_dvol;
+    a.launch.dfeat = fg ? fg->dfeat : nullptr;
+    a.launch.dgmax = fg ? fg->dgmax : nullptr;
     hipError_t e = dvr::launch_fill_zero(dL_dtf, (int64_t)tf->K * 4, stream);
     if (e == hipSuccess && dL_dvol) e = dvr::launch_fill_zero(dL_dvol, nvox(grid), stream);
+    if (e == hipSuccess && fg) e = dvr::launch_fill_zero(fg->dfeat, 5 * nvox(grid), stream);
+    if (e == hipSuccess && fg) e = dvr::launch_fill_zero(fg->dgmax, 1, stream);
     if (e == hipSuccess) e = dvr::launch_render_backward(a, stream);
     delete[] kc;
     return e == hipSuccess ? DVR_OK : dev_fail(e, "render backward launch");
+}
+
+dvr_status dvr_render_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                               const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
+                               const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
+                               const float *dL_drgba, float *dL_dtf, float *dL_dvol, hipStream_t stream)
+{
+    return render_backward(vol, vol_dtype, grid, feat, tf, rp, cams, ncam, state, dL_drgba, dL_dtf, dL_dvol, nullptr,
+                           stream);
+}
+
+dvr_status dvr_render_backward_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
+                                        const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
+                                        const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,
+                                        const float *dL_drgba, float *dL_dtf, float *dL_dvol,
+                                        const dvr_feature_grads *fg, hipStream_t stream)
+{
+    if (!fg) return fail(DVR_E_NULL, "feature gradients are required");
+    return render_backward(vol, vol_dtype, grid, feat, tf, rp, cams, ncam, state, dL_drgba, dL_dtf, dL_dvol, fg,
+                           stream);
 }
 
 }  // extern "C"

@@ -82,6 +82,10 @@ struct AxisTaps {
     float E2[2 * DVR_MAX_RADIUS + 4];
 };
 
+// Output mode of the feature kernels next to the layouts of dvr_layout: write the six Hessian entries
+// of each voxel ([6][N] FP32) and nothing else.
+constexpr int kHessianOut = 16;
+
 struct ScaleTaps {
     AxisTaps ax[3];  // x, y, z
     float sigma2;    // sigma^2 (mm^2): scale normalization of the Hessian for the eigenvalues
@@ -93,6 +97,20 @@ hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g,
                                  const dvr_features_buf &out, float *ws_fields, float *ws_scalars,
                                  bool fro_pass, hipStream_t st);
 hipError_t launch_init_scalars(float *gmax, float *ws_scalars, hipStream_t st);
+// The six Hessian entries of one scale, [6][N] FP32 in H (z-filtered fields staged in ws_fields, 3N).
+hipError_t launch_hessian(const void *vol, int vol_dt, const dvr_grid &g, const ScaleTaps &taps, float *ws_fields,
+                          float *H, hipStream_t st);
+// Feature-pass adjoint (features_bwd.hip); the arguments are validated by the caller.
+struct FeatBwdPlan {
+    int nsigma;
+    ScaleTaps taps[DVR_MAX_SIGMA];
+    double sigma2[DVR_MAX_SIGMA];
+    double inv2a2, inv2b2, inv2c2;  // 1 / (2 alpha^2), 1 / (2 beta^2), 1 / (2 c^2)
+    double inv2h[3];                // 1 / (2 h_a)
+};
+size_t features_bwd_ws_bytes(const dvr_grid &g, const FeatBwdPlan &p);
+hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid &g, const FeatBwdPlan &p,
+                                    const float *dfeat, const float *dgmax, float *dvol, void *ws, hipStream_t st);
 hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const dvr_features_buf &out, hipStream_t st);
 
 hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, int64_t n, uint32_t *ws,

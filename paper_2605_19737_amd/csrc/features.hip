@@ -196,6 +196,39 @@ static hipError_t launch_xy(const XYArgs &a, const ScaleTaps &taps, hipStream_t 
     return hipGetLastError();
 }
 
+static hipError_t launch_z_any(const void *vol, int vol_dt, const dvr_grid &g, const AxisTaps &tz, float *ws_fields,
+                               hipStream_t st)
+{
+    if (tz.R >= 2 && tz.R <= 10)
+        return (vol_dt == DVR_F32) ? launch_z_r<DVR_F32, 2>(vol, ws_fields, g, tz, st)
+                                   : launch_z_r<DVR_F16, 2>(vol, ws_fields, g, tz, st);
+    const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
+    dim3 zgrid((plane + 255) / 256, g.nz);
+    if (vol_dt == DVR_F32)
+        hipLaunchKernelGGL(k_zpass<DVR_F32>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, tz);
+    else
+        hipLaunchKernelGGL(k_zpass<DVR_F16>, zgrid, dim3(256), 0, st, vol, ws_fields, g.nx, g.ny, g.nz, tz);
+    return hipGetLastError();
+}
+
+hipError_t launch_hessian(const void *vol, int vol_dt, const dvr_grid &g, const ScaleTaps &taps, float *ws_fields,
+                          float *H, hipStream_t st)
+{
+    hipError_t e = launch_z_any(vol, vol_dt, g, taps.ax[2], ws_fields, st);
+    if (e != hipSuccess) return e;
+    XYArgs a = {};
+    a.ws = ws_fields;
+    a.vol = vol;
+    a.grad = H;
+    a.nx = g.nx;
+    a.ny = g.ny;
+    a.nz = g.nz;
+    a.first = 0;
+    a.fro_pass = 0;
+    if (vol_dt == DVR_F32) return launch_xy<DVR_F32, DVR_F32, kHessianOut>(a, taps, st);
+    return launch_xy<DVR_F16, DVR_F32, kHessianOut>(a, taps, st);
+}
+
 hipError_t launch_features_scale(const void *vol, int vol_dt, const dvr_grid &g, const ScaleTaps &taps,
                                  int scale_index, bool last_scale, const dvr_feature_params &fp,
                                  const dvr_features_buf &out, float *ws_fields, float *ws_scalars,

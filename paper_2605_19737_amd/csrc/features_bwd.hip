@@ -1,0 +1,538 @@
+// Feature-pass adjoint for gfx950: dL/dI of the gradient (Sec. 2.3 Eq. 2), the first-scale
+// curvature (Sec. 2.3 Eq. 3), the multi-scale Frangi vesselness (Sec. 1) and |g|_max (the Eq. 4
+// normalizer), given dL/d(g, k, V) per voxel and dL/d|g|_max (what the render adjoint with
+// feature gradients produces).
+//
+// Every linear step of the forward is a per-axis banded matrix: the clamped central difference of
+// the gradient, and per scale and axis the three combined smoothing-and-difference operators
+// (G, D1 G, D2 G) with their one-sided first and last rows.  The adjoint applies the transposes.
+// Per scale:
+//   1. the six Hessian entries are recomputed with the forward's own kernels (Hessian-output mode);
+//   2. k_fb_local (FP64, one lane per voxel) forms dL/dH: the curvature term g g^T / g^T g at the
+//      first scale, and at the voxel's winning scale dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T from
+//      a Jacobi eigen-decomposition; at the first scale it also writes dL/dg + dL/dk dk/dg and
+//      the arg-max key of |g|;
+//   3. k_tx, k_ty, k_tz apply the transposed x, y and z operators (the forward's z-then-y-then-x
+//      order reversed: six fields after x, three after y, one accumulated into dL/dI after z).
+// The winning scale of each voxel is found first (k_fb_win: FP64 eigenvalues and V per scale, the
+// first scale whose V exceeds every earlier one and 0).  Last, dL/d|g|_max goes to the arg-max voxel's
+// gradient (k_fb_gmax) and the transposed central difference of the gradient is added (k_fb_gradT).
+//
+// The band tables are built on the device from the forward's FP32 taps (k_band), so the transpose
+// is that of the operator the forward applies.
+#include <math.h>
+
+#include "common.hpp"
+#include "features_dev.hpp"
+
+namespace dvr {
+
+// B[f][i][d + R]: weight of input i + d in output i of operator f (0: G, 1: D1 G, 2: D2 G) along an
+// axis of n voxels; clamped taps fold onto the end voxels, the first and last rows are one-sided.
+__global__ __launch_bounds__(256) void k_band(AxisTaps t, int n, float *__restrict__ B)
+{
+    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (i >= n) return;
+    const int R = t.R, W = 2 * R + 1;
+    const int cls = (i == 0) ? 1 : (i == n - 1 ? 2 : 0);
+    float *b0 = B + (size_t)i * W, *b1 = B + ((size_t)n + i) * W, *b2 = B + ((size_t)2 * n + i) * W;
+    for (int d = 0; d < W; ++d) {
+        b0[d] = 0.f;
+        b1[d] = 0.f;
+        b2[d] = 0.f;
+    }
+    for (int m = -R; m <= R; ++m) {
+        const int am = m < 0 ? -m : m;
+        const int d = clampi(i + m, 0, n - 1) - i + R;
+        float c1, c2;
+        if (cls == 0) {
+            c1 = m > 0 ? t.D1[am] : (m < 0 ? -t.D1[am] : 0.f);
+            c2 = t.D2[am];
+        } else if (cls == 1) {
+            c1 = t.E1[m + R];
+            c2 = t.E2[m + R];
+        } else {
+            c1 = t.E1[m + 1 + R];
+            c2 = -t.E2[m + 1 + R];
+        }
+        b0[d] += t.G[am];
+        b1[d] += c1;
+        b2[d] += c2;
+    }
+}
+
+template <int DT>
+__device__ __forceinline__ double ldd(const void *p, size_t i)
+{
+    if constexpr (DT == DVR_F32) return (double)reinterpret_cast<const float *>(p)[i];
+    else return (double)__half2float(reinterpret_cast<const __half *>(p)[i]);
+}
+
+// (|l|, l) ascending, as the forward sorts the eigenvalues
+__device__ __forceinline__ bool key_less(double u, double v) { return fabs(u) < fabs(v) || (fabs(u) == fabs(v) && u < v); }
+
+// Frangi bright-tube vesselness of magnitude-sorted eigenvalues (FP64)
+__device__ __forceinline__ double frangi64(double l1, double l2, double l3, double ia, double ib, double ic)
+{
+    if (l2 >= 0.0 || l3 >= 0.0) return 0.0;
+    const double Ra2 = (l2 * l2) / (l3 * l3);
+    const double Rb2 = (l1 * l1) / fabs(l2 * l3);
+    const double S2 = l1 * l1 + l2 * l2 + l3 * l3;
+    return -expm1(-Ra2 * ia) * exp(-Rb2 * ib) * -expm1(-S2 * ic);
+}
+
+// winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0
+__global__ __launch_bounds__(256) void k_fb_win(const float *__restrict__ H, double *__restrict__ best,
+                                                uint8_t *__restrict__ win, int s, double sigma2, double ia, double ib,
+                                                double ic, uint32_t N)
+{
+    const uint32_t v = blockIdx.x * 256u + threadIdx.x;
+    if (v >= N) return;
+    double A[6];
+#pragma unroll
+    for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
+    double lo, mi, hi;
+    eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
+    double a = lo, b = mi, c = hi, t;
+    if (key_less(b, a)) { t = a; a = b; b = t; }
+    if (key_less(c, b)) { t = b; b = c; c = t; }
+    if (key_less(b, a)) { t = a; a = b; b = t; }
+    const double V = frangi64(a, b, c, ia, ib, ic);
+    const double prev = s == 0 ? 0.0 : best[v];
+    if (s == 0) win[v] = 255;
+    if (V > prev) {
+        best[v] = V;
+        win[v] = (uint8_t)s;
+    } else if (s == 0) {
+        best[v] = 0.0;
+    }
+}
+
+// one Jacobi rotation annihilating a_pq (r the third index); v accumulates the rotations
+#define DVR_JROT(p, q, r)                                                                        \
+    if (a[p][q] != 0.0) {                                                                        \
+        if (fabs(a[p][q]) <= 1e-300 || fabs(a[p][q]) <= 1e-19 * (fabs(a[p][p]) + fabs(a[q][q]))) { \
+            a[p][q] = a[q][p] = 0.0;                                                             \
+        } else {                                                                                 \
+            const double th = (a[q][q] - a[p][p]) / (2.0 * a[p][q]);                             \
+            const double tt = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(th * th + 1.0));       \
+            const double cc = 1.0 / sqrt(tt * tt + 1.0), ss = tt * cc;                            \
+            const double apq = a[p][q];                                                          \
+            a[p][p] -= tt * apq;                                                                 \
+            a[q][q] += tt * apq;                                                                 \
+            a[p][q] = a[q][p] = 0.0;                                                             \
+            const double arp = a[r][p], arq = a[r][q];                                           \
+            a[r][p] = a[p][r] = cc * arp - ss * arq;                                             \
+            a[r][q] = a[q][r] = ss * arp + cc * arq;                                             \
+            for (int k = 0; k < 3; ++k) {                                                        \
+                const double vp = V[k][p], vq = V[k][q];                                         \
+                V[k][p] = cc * vp - ss * vq;                                                     \
+                V[k][q] = ss * vp + cc * vq;                                                     \
+            }                                                                                    \
+        }                                                                                        \
+    }
+
+// eigenvalues lam[i] and unit eigenvectors V[.][i] of a symmetric 3x3 (cyclic Jacobi, FP64)
+__device__ __forceinline__ void jacobi3v(const double A6[6], double lam[3], double V[3][3])
+{
+    double a[3][3] = {{A6[0], A6[3], A6[4]}, {A6[3], A6[1], A6[5]}, {A6[4], A6[5], A6[2]}};
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) V[i][j] = i == j ? 1.0 : 0.0;
+    for (int sweep = 0; sweep < 16; ++sweep) {
+        if (a[0][1] == 0.0 && a[0][2] == 0.0 && a[1][2] == 0.0) break;
+        DVR_JROT(0, 1, 2)
+        DVR_JROT(0, 2, 1)
+        DVR_JROT(1, 2, 0)
+    }
+    lam[0] = a[0][0];
+    lam[1] = a[1][1];
+    lam[2] = a[2][2];
+}
+#undef DVR_JROT
+
+// dV/dlambda for magnitude-sorted eigenvalues (0 where V = 0 by the sign rule)
+__device__ __forceinline__ void frangi64_grad(const double l[3], double ia, double ib, double ic, double f[3])
+{
+    f[0] = f[1] = f[2] = 0.0;
+    const double l1 = l[0], l2 = l[1], l3 = l[2];
+    if (l2 >= 0.0 || l3 >= 0.0) return;
+    const double p = l2 * l3;
+    const double Ra2 = l2 * l2 / (l3 * l3), Rb2 = l1 * l1 / p, S2 = l1 * l1 + l2 * l2 + l3 * l3;
+    const double ea = exp(-Ra2 * ia), Fa = 1.0 - ea;
+    const double Fb = exp(-Rb2 * ib);
+    const double ec = exp(-S2 * ic), Fc = 1.0 - ec;
+    const double ga = Fb * Fc * ea * ia;       // dV/dRa2
+    const double gb = -Fa * Fc * Fb * ib;      // dV/dRb2
+    const double gc = Fa * Fb * ec * ic;       // dV/dS2
+    f[0] = gb * (2.0 * l1 / p) + gc * 2.0 * l1;
+    f[1] = ga * (2.0 * l2 / (l3 * l3)) + gb * (-l1 * l1 / (l2 * l2 * l3)) + gc * 2.0 * l2;
+    f[2] = ga * (-2.0 * l2 * l2 / (l3 * l3 * l3)) + gb * (-l1 * l1 / (l2 * l3 * l3)) + gc * 2.0 * l3;
+}
+
+// order-preserving 64-bit key of (|g| rounded to FP32, lowest voxel index on a tie)
+__device__ __forceinline__ unsigned long long gkey(double gn, uint32_t v)
+{
+    return ((unsigned long long)__float_as_uint((float)gn) << 32) | (unsigned long long)(0xffffffffu - v);
+}
+
+template <int DT>
+__global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, const float *__restrict__ H,
+                                                  const float *__restrict__ dfeat, const uint8_t *__restrict__ win,
+                                                  float *__restrict__ Hb, float *__restrict__ dgt,
+                                                  unsigned long long *__restrict__ key, int s, double sigma2, double ia,
+                                                  double ib, double ic, int nx, int ny, int nz, double ih0, double ih1,
+                                                  double ih2)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    const int z = (int)blockIdx.y;
+    const bool live = e < plane;
+    const size_t N = (size_t)plane * (size_t)nz;
+    const uint32_t v = (uint32_t)z * plane + (live ? e : 0u);
+    double Hd[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Hd[k] = live ? (double)H[(size_t)k * N + v] : 0.0;
+    double hb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    unsigned long long kv = 0ull;
+    if (s == 0 && live) {
+        const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
+        const size_t row = (size_t)z * plane + (size_t)y * nx;
+        const double g0 = (ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)) - ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1))) * ih0;
+        const double g1 = (ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x) -
+                           ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x)) * ih1;
+        const double g2 = (ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x) -
+                           ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x)) * ih2;
+        const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+        double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
+        const double dk = dfeat[3 * N + v];
+        if (gg > 0.0 && dk != 0.0) {
+            // k = g^T H g / g^T g: dk/dg = 2 (H g - k g) / g^T g, dk/dH_ab = g_a g_b / g^T g (x2 off-diagonal)
+            const double Hg0 = Hd[0] * g0 + Hd[3] * g1 + Hd[4] * g2;
+            const double Hg1 = Hd[3] * g0 + Hd[1] * g1 + Hd[5] * g2;
+            const double Hg2 = Hd[4] * g0 + Hd[5] * g1 + Hd[2] * g2;
+            const double ig = 1.0 / gg;
+            const double k = (g0 * Hg0 + g1 * Hg1 + g2 * Hg2) * ig;
+            const double c2 = 2.0 * dk * ig;
+            d0 += c2 * (Hg0 - k * g0);
+            d1 += c2 * (Hg1 - k * g1);
+            d2 += c2 * (Hg2 - k * g2);
+            const double c1 = dk * ig;
+            hb[0] += c1 * g0 * g0;
+            hb[1] += c1 * g1 * g1;
+            hb[2] += c1 * g2 * g2;
+            hb[3] += 2.0 * c1 * g0 * g1;
+            hb[4] += 2.0 * c1 * g0 * g2;
+            hb[5] += 2.0 * c1 * g1 * g2;
+        }
+        dgt[v] = (float)d0;
+        dgt[N + v] = (float)d1;
+        dgt[2 * N + v] = (float)d2;
+        kv = gkey(sqrt(gg), v);
+    }
+    if (live && win[v] == (uint8_t)s) {
+        const double dV = dfeat[4 * N + v];
+        if (dV != 0.0) {
+            double A[6], lam[3], Q[3][3];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) A[k] = sigma2 * Hd[k];
+            jacobi3v(A, lam, Q);
+            int o[3] = {0, 1, 2}, t;
+            if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+            if (key_less(lam[o[2]], lam[o[1]])) { t = o[1]; o[1] = o[2]; o[2] = t; }
+            if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+            const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
+            double f[3];
+            frangi64_grad(ls, ia, ib, ic, f);
+            // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice)
+            double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+            for (int i = 0; i < 3; ++i) {
+                const double x0 = Q[0][o[i]], x1 = Q[1][o[i]], x2 = Q[2][o[i]];
+                P[0] += f[i] * x0 * x0;
+                P[1] += f[i] * x1 * x1;
+                P[2] += f[i] * x2 * x2;
+                P[3] += f[i] * x0 * x1;
+                P[4] += f[i] * x0 * x2;
+                P[5] += f[i] * x1 * x2;
+            }
+            const double w = dV * sigma2;
+            hb[0] += w * P[0];
+            hb[1] += w * P[1];
+            hb[2] += w * P[2];
+            hb[3] += 2.0 * w * P[3];
+            hb[4] += 2.0 * w * P[4];
+            hb[5] += 2.0 * w * P[5];
+        }
+    }
+    if (live) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) Hb[(size_t)k * N + v] = (float)hb[k];
+    }
+    if (s == 0) {
+        for (int o = 32; o > 0; o >>= 1) {
+            const unsigned long long w = __shfl_xor(kv, o, 64);
+            kv = w > kv ? w : kv;
+        }
+        if ((threadIdx.x & 63) == 0 && kv != 0ull) atomicMax(key, kv);
+    }
+}
+
+// x: six fields X_e = (operator of entry e along x)^T Hb_e; xx uses D2 G, xy and xz D1 G, the rest G
+__global__ __launch_bounds__(256) void k_tx(const float *__restrict__ Hb, float *__restrict__ X,
+                                            const float *__restrict__ B, int nx, int ny, int nz, int R)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= plane) return;
+    const int z = (int)blockIdx.y;
+    const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
+    const size_t N = (size_t)plane * (size_t)nz;
+    const size_t row = (size_t)z * plane + (size_t)y * nx;
+    const int W = 2 * R + 1;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int i0 = max(0, x - R), i1 = min(nx - 1, x + R);
+    for (int i = i0; i <= i1; ++i) {
+        const int d = x - i + R;
+        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)nx + i) * W + d], b2 = B[((size_t)2 * nx + i) * W + d];
+        const size_t sidx = row + i;
+        acc[0] = fmaf(b2, Hb[sidx], acc[0]);
+        acc[1] = fmaf(b0, Hb[N + sidx], acc[1]);
+        acc[2] = fmaf(b0, Hb[2 * N + sidx], acc[2]);
+        acc[3] = fmaf(b1, Hb[3 * N + sidx], acc[3]);
+        acc[4] = fmaf(b1, Hb[4 * N + sidx], acc[4]);
+        acc[5] = fmaf(b0, Hb[5 * N + sidx], acc[5]);
+    }
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[(size_t)k * N + row + x] = acc[k];
+}
+
+// y: the three z-groups: Y0 = G^T X_xx + (D2 G)^T X_yy + (D1 G)^T X_xy (z operator G),
+// Y1 = G^T X_xz + (D1 G)^T X_yz (z operator D1 G), Y2 = G^T X_zz (z operator D2 G)
+__global__ __launch_bounds__(256) void k_ty(const float *__restrict__ X, float *__restrict__ Y,
+                                            const float *__restrict__ B, int nx, int ny, int nz, int R)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= plane) return;
+    const int z = (int)blockIdx.y;
+    const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
+    const size_t N = (size_t)plane * (size_t)nz;
+    const size_t col = (size_t)z * plane + (size_t)x;
+    const int W = 2 * R + 1;
+    float y0 = 0.f, y1 = 0.f, y2 = 0.f;
+    const int i0 = max(0, y - R), i1 = min(ny - 1, y + R);
+    for (int i = i0; i <= i1; ++i) {
+        const int d = y - i + R;
+        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)ny + i) * W + d], b2 = B[((size_t)2 * ny + i) * W + d];
+        const size_t sidx = col + (size_t)i * nx;
+        y0 = fmaf(b0, X[sidx], y0);
+        y0 = fmaf(b2, X[N + sidx], y0);
+        y0 = fmaf(b1, X[3 * N + sidx], y0);
+        y1 = fmaf(b0, X[4 * N + sidx], y1);
+        y1 = fmaf(b1, X[5 * N + sidx], y1);
+        y2 = fmaf(b0, X[2 * N + sidx], y2);
+    }
+    const size_t o = col + (size_t)y * nx;
+    Y[o] = y0;
+    Y[N + o] = y1;
+    Y[2 * N + o] = y2;
+}
+
+// z: dL/dI += G^T Y0 + (D1 G)^T Y1 + (D2 G)^T Y2 along z
+__global__ __launch_bounds__(256) void k_tz(const float *__restrict__ Y, float *__restrict__ dvol,
+                                            const float *__restrict__ B, int nx, int ny, int nz, int R)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= plane) return;
+    const int z = (int)blockIdx.y;
+    const size_t N = (size_t)plane * (size_t)nz;
+    const int W = 2 * R + 1;
+    float acc = 0.f;
+    const int i0 = max(0, z - R), i1 = min(nz - 1, z + R);
+    for (int i = i0; i <= i1; ++i) {
+        const int d = z - i + R;
+        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)nz + i) * W + d], b2 = B[((size_t)2 * nz + i) * W + d];
+        const size_t sidx = (size_t)i * plane + e;
+        acc = fmaf(b0, Y[sidx], acc);
+        acc = fmaf(b1, Y[N + sidx], acc);
+        acc = fmaf(b2, Y[2 * N + sidx], acc);
+    }
+    dvol[(size_t)z * plane + e] += acc;
+}
+
+// dL/d|g|_max to the arg-max voxel's gradient: d|g|/dg = g / |g|
+template <int DT>
+__global__ void k_fb_gmax(const void *__restrict__ vol, const unsigned long long *__restrict__ key,
+                          const float *__restrict__ dgmax, float *__restrict__ dgt, int nx, int ny, int nz, double ih0,
+                          double ih1, double ih2)
+{
+    if (threadIdx.x != 0) return;
+    const unsigned long long k = *key;
+    const float dm = *dgmax;
+    if (k == 0ull || dm == 0.f) return;
+    const uint32_t v = 0xffffffffu - (uint32_t)(k & 0xffffffffull);
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const size_t N = (size_t)plane * (size_t)nz;
+    const int z = (int)(v / plane), r = (int)(v - (uint32_t)z * plane);
+    const int y = r / nx, x = r - y * nx;
+    const size_t row = (size_t)z * plane + (size_t)y * nx;
+    const double g0 = (ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)) - ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1))) * ih0;
+    const double g1 = (ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x) -
+                       ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x)) * ih1;
+    const double g2 = (ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x) -
+                       ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x)) * ih2;
+    const double gn = sqrt(g0 * g0 + g1 * g1 + g2 * g2);
+    if (!(gn > 0.0)) return;
+    const double c = (double)dm / gn;
+    dgt[v] = (float)((double)dgt[v] + c * g0);
+    dgt[N + v] = (float)((double)dgt[N + v] + c * g1);
+    dgt[2 * N + v] = (float)((double)dgt[2 * N + v] + c * g2);
+}
+
+// transposed clamped central difference along one axis at position c of n (stride st), times 1/(2h)
+__device__ __forceinline__ float d1t(const float *__restrict__ a, size_t j, int c, int n, size_t st)
+{
+    float s = 0.f;
+    if (c >= 1) s += a[j - st];
+    if (c == n - 1) s += a[j];
+    if (c + 1 <= n - 1) s -= a[j + st];
+    if (c == 0) s -= a[j];
+    return s;
+}
+
+__global__ __launch_bounds__(256) void k_fb_gradT(const float *__restrict__ dgt, float *__restrict__ dvol, int nx,
+                                                  int ny, int nz, float ih0, float ih1, float ih2)
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    if (e >= plane) return;
+    const int z = (int)blockIdx.y;
+    const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
+    const size_t N = (size_t)plane * (size_t)nz;
+    const size_t j = (size_t)z * plane + e;
+    float acc = ih0 * d1t(dgt, j, x, nx, 1);
+    acc = fmaf(ih1, d1t(dgt + N, j, y, ny, (size_t)nx), acc);
+    acc = fmaf(ih2, d1t(dgt + 2 * N, j, z, nz, (size_t)plane), acc);
+    dvol[j] += acc;
+}
+
+__global__ void k_zero_u64(unsigned long long *p)
+{
+    if (threadIdx.x == 0) *p = 0ull;
+}
+
+// ------------------------------------------------------------------------------------------------
+static size_t al256(size_t b) { return (b + 255u) & ~(size_t)255u; }
+
+struct BwdWs {
+    unsigned long long *key;
+    float *zws;   // 3N: z-filtered fields of the Hessian recomputation; then Y (3N)
+    float *H;     // 6N: H of the current scale; then X (6N)
+    float *Hb;    // 6N: dL/dH of the current scale
+    float *dgt;   // 3N: dL/dg total
+    double *best; // N
+    uint8_t *win; // N
+    float *band;  // per scale and axis: [3][n_a][2 R_a + 1]
+};
+
+static size_t band_floats(const dvr_grid &g, const FeatBwdPlan &p)
+{
+    const int n[3] = {g.nx, g.ny, g.nz};
+    size_t t = 0;
+    for (int s = 0; s < p.nsigma; ++s)
+        for (int a = 0; a < 3; ++a) t += (size_t)3 * n[a] * (2 * p.taps[s].ax[a].R + 1);
+    return t;
+}
+
+static BwdWs carve(void *ws, const dvr_grid &g, const FeatBwdPlan &p, size_t *total)
+{
+    const size_t N = (size_t)g.nx * g.ny * g.nz;
+    char *b = (char *)ws;
+    size_t o = 0;
+    BwdWs w;
+    w.key = (unsigned long long *)(b + o);
+    o += 256;
+    w.zws = (float *)(b + o);
+    o += al256(12 * N);
+    w.H = (float *)(b + o);
+    o += al256(24 * N);
+    w.Hb = (float *)(b + o);
+    o += al256(24 * N);
+    w.dgt = (float *)(b + o);
+    o += al256(12 * N);
+    w.best = (double *)(b + o);
+    o += al256(8 * N);
+    w.win = (uint8_t *)(b + o);
+    o += al256(N);
+    w.band = (float *)(b + o);
+    o += al256(4 * band_floats(g, p));
+    if (total) *total = o;
+    return w;
+}
+
+size_t features_bwd_ws_bytes(const dvr_grid &g, const FeatBwdPlan &p)
+{
+    size_t t = 0;
+    carve(nullptr, g, p, &t);
+    return t;
+}
+
+hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid &g, const FeatBwdPlan &p,
+                                    const float *dfeat, const float *dgmax, float *dvol, void *ws, hipStream_t st)
+{
+    const BwdWs w = carve(ws, g, p, nullptr);
+    const int n[3] = {g.nx, g.ny, g.nz};
+    const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
+    const uint32_t N = plane * (uint32_t)g.nz;
+    const dim3 pgrid((plane + 255) / 256, g.nz);
+    const dim3 vgrid((N + 255) / 256);
+    hipError_t e;
+    // band tables of every scale and axis
+    float *bt[DVR_MAX_SIGMA][3];
+    {
+        float *b = w.band;
+        for (int s = 0; s < p.nsigma; ++s)
+            for (int a = 0; a < 3; ++a) {
+                bt[s][a] = b;
+                hipLaunchKernelGGL(k_band, dim3((n[a] + 255) / 256), dim3(256), 0, st, p.taps[s].ax[a], n[a], b);
+                b += (size_t)3 * n[a] * (2 * p.taps[s].ax[a].R + 1);
+            }
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.key);
+    // winning scale of each voxel
+    for (int s = 0; s < p.nsigma; ++s) {
+        if ((e = launch_hessian(vol, vol_dt, g, p.taps[s], w.zws, w.H, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fb_win, vgrid, dim3(256), 0, st, w.H, w.best, w.win, s, p.sigma2[s], p.inv2a2, p.inv2b2,
+                           p.inv2c2, N);
+    }
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    for (int s = 0; s < p.nsigma; ++s) {
+        if ((e = launch_hessian(vol, vol_dt, g, p.taps[s], w.zws, w.H, st)) != hipSuccess) return e;
+        if (vol_dt == DVR_F32)
+            hipLaunchKernelGGL(k_fb_local<DVR_F32>, pgrid, dim3(256), 0, st, vol, w.H, dfeat, w.win, w.Hb, w.dgt, w.key,
+                               s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
+                               p.inv2h[2]);
+        else
+            hipLaunchKernelGGL(k_fb_local<DVR_F16>, pgrid, dim3(256), 0, st, vol, w.H, dfeat, w.win, w.Hb, w.dgt, w.key,
+                               s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
+                               p.inv2h[2]);
+        float *X = w.H, *Y = w.zws;
+        hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
+        hipLaunchKernelGGL(k_ty, pgrid, dim3(256), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
+        hipLaunchKernelGGL(k_tz, pgrid, dim3(256), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+    if (vol_dt == DVR_F32)
+        hipLaunchKernelGGL(k_fb_gmax<DVR_F32>, dim3(1), dim3(64), 0, st, vol, w.key, dgmax, w.dgt, g.nx, g.ny, g.nz,
+                           p.inv2h[0], p.inv2h[1], p.inv2h[2]);
+    else
+        hipLaunchKernelGGL(k_fb_gmax<DVR_F16>, dim3(1), dim3(64), 0, st, vol, w.key, dgmax, w.dgt, g.nx, g.ny, g.nz,
+                           p.inv2h[0], p.inv2h[1], p.inv2h[2]);
+    hipLaunchKernelGGL(k_fb_gradT, pgrid, dim3(256), 0, st, w.dgt, dvol, g.nx, g.ny, g.nz, (float)p.inv2h[0],
+                       (float)p.inv2h[1], (float)p.inv2h[2]);
+    return hipGetLastError();
+}
+
+}  // namespace dvr

@@ -241,6 +241,13 @@ template <int OUT_DT, int LAYOUT>
 __device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const float H[6], const float In[7], uint32_t v,
                                           uint32_t N, float &vmax)
 {
+    if constexpr (LAYOUT == kHessianOut) {
+        // the adjoint's recomputation: H itself, [6][N] FP32 in a.grad
+        float *Ho = reinterpret_cast<float *>(a.grad);
+#pragma unroll
+        for (int e = 0; e < 6; ++e) Ho[(size_t)e * N + v] = H[e];
+        return;
+    }
     float A[6];
     for (int e = 0; e < 6; ++e) A[e] = sigma2 * H[e];
     if (a.fro_pass) {

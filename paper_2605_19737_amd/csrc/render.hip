@@ -101,7 +101,7 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
     if (L.counters) count_samples(L.counters, o.last, o.shaded);
 }
 
-template <int LAYOUT, int DT, int KMAX>
+template <int LAYOUT, int DT, int KMAX, bool FG>
 __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf, KRender rp, KLaunch L)
 {
     __shared__ TFShared<KMAX> sh;
@@ -134,8 +134,13 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
         Tl = L.T_last[pix];
     }
     // every lane of the wave takes part (the dL/dI window is managed wave-wide)
-    march_bwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r, kl, Tl, gr, K, tfa + (threadIdx.x % kCopies), L.dvol,
-                                wwin);
+    float gmb = 0.f;
+    march_bwd<LAYOUT, DT, KMAX, FG>(feat, g, sh, kx, rp, invg, r, kl, Tl, gr, K, tfa + (threadIdx.x % kCopies), L.dvol,
+                                    wwin, L.dfeat, gmb);
+    if constexpr (FG) {
+        for (int o = 32; o > 0; o >>= 1) gmb += __shfl_xor(gmb, o, 64);
+        if ((threadIdx.x & 63) == 0 && gmb != 0.f) atomicAdd(L.dgmax, gmb);
+    }
     __syncthreads();
     for (int p = threadIdx.x; p < K * 4; p += 256) {
         double acc = 0.0;
@@ -150,8 +155,10 @@ template <int LAYOUT, int DT, int KMAX>
 static hipError_t launch_fwd_t(const KFeat &f, const KGrid &g, const KTF &tf, const KRender &rp, const KLaunch &L,
                                uint32_t blocks, hipStream_t st, bool bwd)
 {
-    if (bwd)
-        hipLaunchKernelGGL((k_render_bwd<LAYOUT, DT, KMAX>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
+    if (bwd && L.dfeat)
+        hipLaunchKernelGGL((k_render_bwd<LAYOUT, DT, KMAX, true>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
+    else if (bwd)
+        hipLaunchKernelGGL((k_render_bwd<LAYOUT, DT, KMAX, false>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
     else
         hipLaunchKernelGGL((k_render<LAYOUT, DT, KMAX>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
     return hipGetLastError();

@@ -48,6 +48,8 @@ struct KLaunch {
     const float *dout;      // backward: dL/d rgba
     float *dtf;             // backward: dL/d TF values [K][4]
     float *dvol;            // backward: dL/d I [N] or null
+    float *dfeat = nullptr;  // backward with feature gradients: dL/d(gx, gy, gz, k, V) as [5][N], or null
+    float *dgmax = nullptr;  // backward with feature gradients: dL/d gmax [1]
     unsigned long long *counters;  // forward: evaluated samples, shaded samples (or null)
     KCam cams[kCamChunk];
 };

@@ -661,15 +661,22 @@ struct DWin {
 // flushes to a workgroup array in LDS (LDS atomics) when the segment changes; the workgroup array
 // is added to the global [K][4] gradient with one atomic per parameter at the end.
 //
+// FG (feature gradients): with x = tau M delta_k and M = m w u, dL/dM = dL/dalpha (1 - alpha) tau delta_k
+// is taken through m = (1 - lg) + lg min(|g| / gmax, 1) (to the interpolated g and to gmax, nothing
+// where the ratio is clamped at 1), w = (1 - lk) + lk |k| / (|k| + k0) (nothing at k = 0) and
+// u = 1 + lv V, and scattered to the 8 corners of [5][N] dfeat with the trilinear weights (global
+// float atomics); the gmax part is summed in gmb.
+//
 // Every lane of the wave calls this (kl = -1 for a lane without a ray).  The loop runs over the
 // sample index k from the wave's largest k_last down to 0, a lane taking part once k <= its own
 // k_last, so at each step the lanes sit at the same sample index (the same depth for rays that
 // entered through the same face) and the loop control stays wave-uniform for the dL/dI window.
-template <int LAYOUT, int DT, int KMAX>
+template <int LAYOUT, int DT, int KMAX, bool FG>
 __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, const TFShared<KMAX> &sh,
                                           const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r,
                                           int kl, float T_last, float4 gr, int K, double *tfa, float *dvol,
-                                          double *win /* this wave's kWin entries of LDS, zeroed */)
+                                          double *win /* this wave's kWin entries of LDS, zeroed */,
+                                          float *dfeat, float &gmb)
 {
     const float gC0 = gr.x, gC1 = gr.y, gC2 = gr.z, gA = gr.w;
     float T = T_last;
@@ -725,6 +732,36 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
             vb[1] = gC1 * Ta;
             vb[2] = gC2 * Ta;
             vb[3] = dal * o.om * o.M * dk;
+            if constexpr (FG) {
+                const float Mb = dal * o.om * o.tau * dk;
+                if (Mb != 0.f) {
+                    const float gn = __builtin_amdgcn_sqrtf(ch.g[0] * ch.g[0] + ch.g[1] * ch.g[1] + ch.g[2] * ch.g[2]);
+                    const float t = gn * invg;
+                    const float m = fmaf(rp.lg, fminf(t, 1.f), rp.omlg);
+                    const float ak = fabsf(ch.k);
+                    const float rk = 1.f / (ak + rp.k0);
+                    const float w = fmaf(rp.lk, ak * rk, rp.omlk);
+                    const float u = fmaf(rp.lv, ch.V, 1.f);
+                    float gs = 0.f;
+                    if (t < 1.f && gn > 0.f) {
+                        const float mb = Mb * w * u * rp.lg;
+                        gs = mb * invg / gn;
+                        gmb -= mb * t * invg;
+                    }
+                    const float sk = ch.k > 0.f ? 1.f : (ch.k < 0.f ? -1.f : 0.f);
+                    const float kb = Mb * m * u * rp.lk * rp.k0 * sk * rk * rk;
+                    const float vb = Mb * m * w * rp.lv;
+                    const float val[5] = {gs * ch.g[0], gs * ch.g[1], gs * ch.g[2], kb, vb};
+                    const uint32_t N = (uint32_t)g.n[0] * (uint32_t)g.n[1] * (uint32_t)g.n[2];
+#pragma unroll
+                    for (int e = 0; e < 8; ++e) {
+                        const uint32_t vi = (c.off[e >> 1] + ((e & 1) ? vx.sx : 0u)) >> esh;
+#pragma unroll
+                        for (int f = 0; f < 5; ++f)
+                            if (val[f] != 0.f) atomicAdd(dfeat + (size_t)f * N + vi, c.w[e] * val[f]);
+                    }
+                }
+            }
             S0 = fmaf(o.om, S0, o.alpha * o.c[0]);
             S1 = fmaf(o.om, S1, o.alpha * o.c[1]);
             S2 = fmaf(o.om, S2, o.alpha * o.c[2]);

@@ -129,3 +129,35 @@ def render_pixel(vol, g, kap, ves, gmax, spacing, knots, rgba, prm, cam, i, j):
         out[:3] += trans * a[k] * col[k, :3]
     out[3] = 1.0 - np.prod(1.0 - a[:keep])
     return out, keep
+
+
+def near_knot_voxels(shape_zyx, spacing, I, knots, prm, cams, eps=1e-6):
+    """Voxels that are trilinear corners of a sample whose intensity lies within eps of a TF knot.
+    There the TF slope jumps, so FP32 and FP64 evaluations may take different segments and the
+    intensity gradient of that one sample differs by O(1): a tolerated set for dL/dI comparisons."""
+    nz, ny, nx = shape_zyx
+    h = np.asarray(spacing, np.float64)
+    hi = np.array([(nx - 1) * h[0], (ny - 1) * h[1], (nz - 1) * h[2]])
+    mask = np.zeros(shape_zyx, bool)
+    kn = np.asarray(knots, np.float64)
+    delta = prm["step_vox"] * h.min()
+    for cam in cams:
+        pk = cam.packed()
+        for j in range(cam.height):
+            for i in range(cam.width):
+                o, d = ray_of(pk, i, j)
+                cl = clip_faces(o, d, hi)
+                if cl is None:
+                    continue
+                L = cl[1] - cl[0]
+                N = int(math.ceil(L / delta))
+                dks = np.full(N, delta)
+                dks[-1] = L - (N - 1) * delta
+                tk = cl[0] + np.arange(N) * delta + 0.5 * dks
+                Q = np.clip((o[None] + tk[:, None] * d[None]) / h, 0, [nx - 1, ny - 1, nz - 1])
+                Iq = ndi.map_coordinates(I, np.stack([Q[:, 2], Q[:, 1], Q[:, 0]]), order=1, mode="nearest")
+                near = np.abs(Iq[:, None] - kn[None]).min(1) < eps
+                for q in Q[near]:
+                    c = np.minimum(np.floor(q).astype(int), [nx - 2, ny - 2, nz - 2])
+                    mask[c[2]:c[2] + 2, c[1]:c[1] + 2, c[0]:c[0] + 2] = True
+    return mask

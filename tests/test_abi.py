@@ -213,3 +213,43 @@ def test_bricks_count_and_alignment(L):
     s, msg = _status(L, "dvr_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fp()),
                      C.byref(fb), C.c_void_p(FAKE), 1 << 30, None)
     assert s == -3 and "bricks" in msg
+
+
+def test_feature_adjoint_validation(L):
+    """dvr_features_backward and dvr_render_backward_features reject bad arguments before any
+    device work: Frangi's c must be given (> 0), the upstream gradients and dL/dvol are required,
+    the workspace is 256-byte aligned and large enough, the volume F32 or F16."""
+    g, fp = _grid(), _fp()
+    n = C.c_size_t()
+    assert L.dvr_features_backward_workspace(C.byref(g), C.byref(fp), C.byref(n)) == 0
+    N = 8 * 9 * 10
+    assert n.value >= 81 * N
+    assert L.dvr_features_backward_workspace(C.byref(g), C.byref(_fp(c=0.0)), C.byref(n)) == -1
+    fg = abi.FeatureGrads(FAKE, FAKE)
+    ws = C.c_void_p(FAKE * 16)  # 256-byte aligned
+    big = 1 << 30
+
+    def call(vol=C.c_void_p(FAKE), dt=abi.DVR_F32, fpp=fp, fgp=C.byref(fg), dvol=C.c_void_p(FAKE), w=ws, wb=big):
+        return _status(L, "dvr_features_backward", vol, dt, C.byref(g), C.byref(fpp), fgp, dvol, w, wb, None)
+
+    assert call(fpp=_fp(c=-1.0))[0] == -1
+    assert call(fgp=None)[0] == -2
+    assert call(fgp=C.byref(abi.FeatureGrads(FAKE, None)))[0] == -2
+    assert call(dvol=None)[0] == -2
+    assert call(dvol=C.c_void_p(FAKE + 2))[0] == -3
+    assert call(w=C.c_void_p(FAKE + 16))[0] == -3
+    s, msg = call(wb=64)
+    assert s == -9 and "workspace" in msg
+    assert call(dt=abi.DVR_U16)[0] == -4
+    assert call(vol=None)[0] == -2
+    arr = (abi.Camera * 1)(_cam())
+    tf = abi.TF(4, FAKE, FAKE)
+    st = abi.RayState(FAKE, FAKE, None)
+    s, _ = _status(L, "dvr_render_backward_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fb()),
+                   C.byref(tf), C.byref(_rp()), arr, 1, C.byref(st), C.c_void_p(FAKE), C.c_void_p(FAKE), None, None,
+                   None)
+    assert s == -2
+    s, _ = _status(L, "dvr_render_backward_features", C.c_void_p(FAKE), abi.DVR_F32, C.byref(_grid()), C.byref(_fb()),
+                   C.byref(tf), C.byref(_rp()), arr, 1, C.byref(st), C.c_void_p(FAKE), C.c_void_p(FAKE), None,
+                   C.byref(abi.FeatureGrads(FAKE + 2, FAKE)), None)
+    assert s == -3
