@@ -107,13 +107,14 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
     __shared__ TFShared<KMAX> sh;
     constexpr int kCopies = tf_copies(KMAX);
     __shared__ double tfa[KMAX * 4 * kCopies];
-    __shared__ double win[4][kWin];  // one dL/dI accumulation window per wave
+    using Win = std::conditional_t<FG, DWinF, DWin>;
+    __shared__ double win[4][Win::kEntries];  // one accumulation window per wave
     float kx[KMAX];
     tf_load<KMAX>(sh, kx, tf);
     for (int p = threadIdx.x; p < KMAX * 4 * kCopies; p += 256) tfa[p] = 0.0;
     double *wwin = win[threadIdx.x >> 6];
-    if (L.dvol)
-        for (int p = threadIdx.x & 63; p < kWin; p += 64) wwin[p] = 0.0;
+    if (FG || L.dvol)
+        for (int p = threadIdx.x & 63; p < Win::kEntries; p += 64) wwin[p] = 0.0;
     __syncthreads();
     const int K = tf.K;
     uint32_t cam;

@@ -4,6 +4,8 @@
 
 #include <math.h>
 
+#include <type_traits>
+
 #include "common.hpp"
 #include "render_args.hpp"
 
@@ -531,7 +533,11 @@ struct SegAcc {
 // advance on fastest and its shortest along the slowest (fixed per wave at its first placement).
 // Entries are FP64: LDS atomic adds on FP64 run at about the rate of integer ones on this chip,
 // while FP32 LDS atomic adds are many times slower.
-constexpr int kWin0 = 16, kWin1 = 12, kWin2 = 8, kWin = kWin0 * kWin1 * kWin2;
+// With feature gradients the window holds six channels per voxel (I, gx, gy, gz, k, V) over a
+// smaller box, so that the four windows of a workgroup still fit beside the occupancy the
+// registers allow.
+constexpr int kWin0 = 16, kWin1 = 12, kWin2 = 8;
+constexpr int kFWin0 = 6, kFWin1 = 8, kFWin2 = 8;
 
 __device__ __forceinline__ int wave_min_i(int v)
 {
@@ -548,15 +554,15 @@ __device__ __forceinline__ int wave_max_i(int v)
 // Pairwise merge inside each quad of lanes (xor 1, then xor 2): where both lanes of a pair hold the
 // same key, the lower lane adds the upper lane's values and the upper lane drops out.  Keys must be
 // unique for lanes without values.  All lanes of the wave must be active.
-template <int CTRL, int BIT>
-__device__ __forceinline__ void quad_merge_step(bool &has, int key, float (&v)[8])
+template <int CTRL, int BIT, int NV>
+__device__ __forceinline__ void quad_merge_step(bool &has, int key, float (&v)[NV])
 {
     const int pk = __builtin_amdgcn_update_dpp(0, key, CTRL, 0xF, 0xF, false);
     const int ph = __builtin_amdgcn_update_dpp(0, has ? 1 : 0, CTRL, 0xF, 0xF, false);
     const bool same = (pk == key);
     const bool upper = ((threadIdx.x >> BIT) & 1u) != 0u;
 #pragma unroll
-    for (int e = 0; e < 8; ++e) {
+    for (int e = 0; e < NV; ++e) {
         const float pv =
             __builtin_bit_cast(float, __builtin_amdgcn_update_dpp(0, __builtin_bit_cast(int, v[e]), CTRL, 0xF, 0xF, false));
         v[e] = same ? (upper ? 0.f : v[e] + pv) : v[e];
@@ -564,14 +570,19 @@ __device__ __forceinline__ void quad_merge_step(bool &has, int key, float (&v)[8
     has = same ? (!upper && (has || ph != 0)) : has;
 }
 
-__device__ __forceinline__ void quad_merge(bool &has, int key, float (&v)[8])
+template <int NV>
+__device__ __forceinline__ void quad_merge(bool &has, int key, float (&v)[NV])
 {
     quad_merge_step<0xB1, 0>(has, key, v);  // quad_perm [1,0,3,2]: partner lane ^ 1
     quad_merge_step<0x4E, 1>(has, key, v);  // quad_perm [2,3,0,1]: partner lane ^ 2
 }
 
-struct DWin {
-    double *w;    // this wave's kWin entries in LDS, index u0 + kWin0 (u1 + kWin1 u2)
+template <int W0, int W1, int W2, int CH>
+struct DWinT {
+    static constexpr int kVox = W0 * W1 * W2;      // voxels of the window
+    static constexpr int kEntries = kVox * CH;     // doubles in LDS
+    static_assert(kVox % 64 == 0, "whole flush rounds");
+    double *w;    // this wave's kEntries in LDS: [voxel u0 + W0 (u1 + W1 u2)][channel]
     int o[3];     // voxel index (x, y, z) of the window's first entry; wave-uniform
     int ext[3];   // window extent along voxel axis x, y, z
     int st[3];    // window index stride of voxel axis x, y, z
@@ -587,8 +598,8 @@ struct DWin {
         r[0] = (ay > ax) + (az > ax);
         r[1] = (ax >= ay) + (az > ay);
         r[2] = (ax >= az) + (ay >= az);
-        const int W[3] = {kWin0, kWin1, kWin2};
-        const int S[3] = {1, kWin0, kWin0 * kWin1};
+        const int W[3] = {W0, W1, W2};
+        const int S[3] = {1, W0, W0 * W1};
         const int G[3] = {1, g.n[0], g.n[0] * g.n[1]};
 #pragma unroll
         for (int a = 0; a < 3; ++a) {
@@ -604,21 +615,26 @@ struct DWin {
         for (int e = 0; e < 8; ++e) crn[e] = (e & 1) * st[0] + ((e >> 1) & 1) * st[1] + ((e >> 2) & 1) * st[2];
     }
 
-    // add every non-zero entry to dvol and clear it (all lanes of the wave)
-    __device__ __forceinline__ void flush(float *dvol, const KGrid &g)
+    // add every non-zero entry to its output and clear it (all lanes of the wave): channel 0 to
+    // dvol, channel c > 0 to dfeat[c - 1][.]
+    __device__ __forceinline__ void flush(float *dvol, float *dfeat, const KGrid &g)
     {
         const int lane = threadIdx.x & 63;
         const int olin = o[0] + o[1] * g.n[0] + o[2] * g.n[0] * g.n[1];
+        const size_t N = (size_t)g.n[0] * (size_t)g.n[1] * (size_t)g.n[2];
 #pragma unroll 4
-        for (int j = 0; j < kWin / 64; ++j) {
+        for (int j = 0; j < kVox / 64; ++j) {
             const int e = lane + 64 * j;
-            const double v = w[e];
-            if (v != 0.0) {
-                const int u0 = e % kWin0, u1 = (e / kWin0) % kWin1, u2 = e / (kWin0 * kWin1);
-                // entries are only ever written for in-bounds voxels, so gi is in [0, N)
-                const int gi = olin + u0 * gst[0] + u1 * gst[1] + u2 * gst[2];
-                atomicAdd(dvol + gi, (float)v);
-                w[e] = 0.0;
+            const int u0 = e % W0, u1 = (e / W0) % W1, u2 = e / (W0 * W1);
+            // entries are only ever written for in-bounds voxels, so gi is in [0, N)
+            const int gi = olin + u0 * gst[0] + u1 * gst[1] + u2 * gst[2];
+#pragma unroll
+            for (int c = 0; c < CH; ++c) {
+                const double v = w[e * CH + c];
+                if (v != 0.0) {
+                    atomicAdd(c == 0 ? dvol + gi : dfeat + (size_t)(c - 1) * N + gi, (float)v);
+                    w[e * CH + c] = 0.0;
+                }
             }
         }
     }
@@ -650,6 +666,9 @@ struct DWin {
     }
 };
 
+using DWin = DWinT<kWin0, kWin1, kWin2, 1>;
+using DWinF = DWinT<kFWin0, kFWin1, kFWin2, 6>;
+
 // Adjoint (back to front from the stored (T_last, k_last)).  With suffix colour S and suffix
 // transmittance R of the samples behind k:
 //   dL/dalpha_k = T_k (gC . (c_k - S) + gA R),   dL/dc_k = gC T_k alpha_k,
@@ -675,7 +694,7 @@ template <int LAYOUT, int DT, int KMAX, bool FG>
 __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, const TFShared<KMAX> &sh,
                                           const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r,
                                           int kl, float T_last, float4 gr, int K, double *tfa, float *dvol,
-                                          double *win /* this wave's kWin entries of LDS, zeroed */,
+                                          double *win /* this wave's window entries of LDS, zeroed */,
                                           float *dfeat, float &gmb)
 {
     const float gC0 = gr.x, gC1 = gr.y, gC2 = gr.z, gA = gr.w;
@@ -693,15 +712,67 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
     for (int e = 0; e < 4; ++e) sa.lo[e] = sa.hi[e] = 0.f;
     CornerCache<LAYOUT, DT> cc;
     cc.reset();
-    DWin dw;
+    using Win = std::conditional_t<FG, DWinF, DWin>;
+    Win dw;
     dw.w = win;
     dw.live = false;
     bool oriented = false;
     dw.o[0] = dw.o[1] = dw.o[2] = 0;
+    // FG: this lane's running sums for the 8 corners of cell acell (see the loop)
+    float acc[48];  // [corner][channel]
+    int acell[3] = {-1, -1, -1};
+    bool ahas = false;
+#pragma unroll
+    for (int e = 0; e < 48; ++e) acc[e] = 0.f;
+    // all lanes call: lanes with flag set add acc to the window (placing it again if needed) or, when
+    // their cell does not fit, to global memory
+    auto emit_cell = [&](bool flag) {
+        if constexpr (FG) {
+            bool in = flag && dw.live && dw.holds(acell);
+            const uint64_t miss = __ballot(flag && !in);
+            if (miss) {
+                const int lead = __ffsll((unsigned long long)miss) - 1;
+                int64_t dql[3];
+                for (int a = 0; a < 3; ++a) dql[a] = __shfl(r.dq[a], lead, 64);
+                if (dw.live) dw.flush(dvol, dfeat, g);
+                if (!oriented) {
+                    dw.orient(dql, g);
+                    oriented = true;
+                }
+                dw.place(flag, acell, dql);
+                in = flag && dw.holds(acell);
+            }
+            if (in) {
+                const int b = dw.index(acell);
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    double *p = win + (b + dw.crn[e]) * 6;
+#pragma unroll
+                    for (int ch6 = 0; ch6 < 6; ++ch6)
+                        if (acc[e * 6 + ch6] != 0.f)
+                            __hip_atomic_fetch_add(p + ch6, (double)acc[e * 6 + ch6], __ATOMIC_RELAXED,
+                                                   __HIP_MEMORY_SCOPE_WAVEFRONT);
+                }
+            } else if (flag) {
+                const uint32_t nx = (uint32_t)g.n[0], plane = nx * (uint32_t)g.n[1];
+                const size_t N = (size_t)plane * (size_t)g.n[2];
+                const uint32_t v0 = (uint32_t)acell[2] * plane + (uint32_t)acell[1] * nx + (uint32_t)acell[0];
+#pragma unroll
+                for (int e = 0; e < 8; ++e) {
+                    const uint32_t vi = v0 + (e & 1) + ((e >> 1) & 1) * nx + ((e >> 2) & 1) * plane;
+                    if (acc[e * 6] != 0.f) atomicAdd(dvol + vi, acc[e * 6]);
+#pragma unroll
+                    for (int f = 1; f < 6; ++f)
+                        if (acc[e * 6 + f] != 0.f) atomicAdd(dfeat + (size_t)(f - 1) * N + vi, acc[e * 6 + f]);
+                }
+            }
+        }
+    };
     const int kmax = __builtin_amdgcn_readfirstlane(wave_max_i(kl));
     for (int k = kmax; k >= 0; --k) {
         const bool act = (k <= kl);
         float Ib = 0.f;
+        float fv[5] = {0.f, 0.f, 0.f, 0.f, 0.f};  // FG: this sample's dL/d(gx, gy, gz, k, V)
         Corners c;
         int cell[3] = {0, 0, 0};
         if (act) {
@@ -749,17 +820,11 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                         gmb -= mb * t * invg;
                     }
                     const float sk = ch.k > 0.f ? 1.f : (ch.k < 0.f ? -1.f : 0.f);
-                    const float kb = Mb * m * u * rp.lk * rp.k0 * sk * rk * rk;
-                    const float vb = Mb * m * w * rp.lv;
-                    const float val[5] = {gs * ch.g[0], gs * ch.g[1], gs * ch.g[2], kb, vb};
-                    const uint32_t N = (uint32_t)g.n[0] * (uint32_t)g.n[1] * (uint32_t)g.n[2];
-#pragma unroll
-                    for (int e = 0; e < 8; ++e) {
-                        const uint32_t vi = (c.off[e >> 1] + ((e & 1) ? vx.sx : 0u)) >> esh;
-#pragma unroll
-                        for (int f = 0; f < 5; ++f)
-                            if (val[f] != 0.f) atomicAdd(dfeat + (size_t)f * N + vi, c.w[e] * val[f]);
-                    }
+                    fv[0] = gs * ch.g[0];
+                    fv[1] = gs * ch.g[1];
+                    fv[2] = gs * ch.g[2];
+                    fv[3] = Mb * m * u * rp.lk * rp.k0 * sk * rk * rk;
+                    fv[4] = Mb * m * w * rp.lv;
                 }
             }
             S0 = fmaf(o.om, S0, o.alpha * o.c[0]);
@@ -785,7 +850,31 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 Ib = vb[0] * s.x + vb[1] * s.y + vb[2] * s.z + vb[3] * s.w;
             }
         }
-        if (dvol) {
+        if constexpr (FG) {
+            // six channels (I, gx, gy, gz, k, V): a lane sums its cell's 8 corners in registers while
+            // its ray stays in that cell and emits them when the cell changes (neighbouring rays in
+            // one cell would otherwise add to the same LDS entries in the same instruction)
+            const float val[6] = {dvol ? Ib : 0.f, fv[0], fv[1], fv[2], fv[3], fv[4]};
+            const bool nz = act && (val[0] != 0.f || val[1] != 0.f || val[2] != 0.f || val[3] != 0.f ||
+                                    val[4] != 0.f || val[5] != 0.f);
+            const bool moved = act && (cell[0] != acell[0] || cell[1] != acell[1] || cell[2] != acell[2]);
+            emit_cell(ahas && moved);
+            if (moved) {
+#pragma unroll
+                for (int e = 0; e < 48; ++e) acc[e] = 0.f;
+                acell[0] = cell[0];
+                acell[1] = cell[1];
+                acell[2] = cell[2];
+                ahas = false;
+            }
+            if (nz) {
+#pragma unroll
+                for (int e = 0; e < 8; ++e)
+#pragma unroll
+                    for (int ch6 = 0; ch6 < 6; ++ch6) acc[e * 6 + ch6] = fmaf(c.w[e], val[ch6], acc[e * 6 + ch6]);
+                ahas = true;
+            }
+        } else if (dvol) {
             bool need = act && Ib != 0.f;
             float cw[8];
 #pragma unroll
@@ -800,7 +889,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 const int lead = __ffsll((unsigned long long)miss) - 1;
                 int64_t dql[3];
                 for (int a = 0; a < 3; ++a) dql[a] = __shfl(r.dq[a], lead, 64);
-                if (dw.live) dw.flush(dvol, g);
+                if (dw.live) dw.flush(dvol, dfeat, g);
                 if (!oriented) {
                     dw.orient(dql, g);
                     oriented = true;
@@ -831,7 +920,8 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
             q[2] -= from_last ? r.dql[2] : r.dq[2];
         }
     }
-    if (dvol && dw.live) dw.flush(dvol, g);
+    if constexpr (FG) emit_cell(ahas);
+    if ((FG || dvol) && dw.live) dw.flush(dvol, dfeat, g);
     if (sa.seg != -2) sa.flush(tfa, K);
 }
 
