@@ -75,6 +75,7 @@ def main():
     ap.add_argument("--no-fp16-leg", action="store_true")
     ap.add_argument("--no-batch-leg", action="store_true")
     ap.add_argument("--no-c5-leg", action="store_true")
+    ap.add_argument("--no-feature-adjoint-leg", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="just the timed head-phantom steps (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
@@ -181,6 +182,7 @@ def main():
     # ------------------------------------------------------------------ fwd+bwd ms/view leg
     if args.only_main:
         args.no_backward_leg = args.no_fp16_leg = args.no_batch_leg = args.no_c5_leg = True
+        args.no_feature_adjoint_leg = True
         args.no_cpu_baseline = True
     if not args.no_fp16_leg:
         comps["fp16_records"] = leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log)
@@ -214,6 +216,9 @@ def main():
         comps.update({"fwd_bwd_ms_per_view": (fw + bw) / len(c3), "fwd_ms_per_view": fw / len(c3),
                       "bwd_ms_per_view": bw / len(c3), "fwd_bwd_workload": "128^3 phantom, 8 ortho views 512^2, 16-knot TF"})
         log(f"fwd+bwd {comps['fwd_bwd_ms_per_view']:.3f} ms/view (fwd {fw / 8:.3f}, bwd {bw / 8:.3f})")
+
+    if not args.no_feature_adjoint_leg:
+        comps["feature_adjoint"] = leg_feature_adjoint(w, vol, feats, knots, tf, cams, stream, dvr, torch, np, log)
 
     if args.copy_calibration:
         src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
@@ -257,6 +262,49 @@ def main():
                       "voxels": nvox, "views": V, "image": [1024, 1024]},
            "roofline": roofline, "cpu_baseline": cpu, "components": comps}
     print(json.dumps(out), flush=True)
+
+
+def leg_feature_adjoint(w, vol, feats, knots, tf, cams, stream, dvr, torch, np, log):
+    """Gradient through the morphology terms on the head: the render adjoint with feature gradients
+    (8 views spread over the orbit) against the plain adjoint, and the feature-pass adjoint (3 scales)
+    that takes dL/d(g, k, V, gmax) to dL/dI."""
+    log("feature-adjoint leg: head, 8 views, render adjoint with feature gradients + feature-pass adjoint")
+    sel = cams[:: max(1, len(cams) // 8)][:8]
+    img, T, k = dvr.render(vol, feats, knots, tf, w.params, sel)
+    dout = torch.randn(img.shape, generator=torch.Generator(device=img.device).manual_seed(7), device=img.device)
+    dvol = torch.zeros_like(vol)
+    nfb = dvr.features_backward_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c)
+    wsb = torch.empty(nfb, dtype=torch.uint8, device=vol.device)
+
+    def timed(fn, reps=3):
+        fn()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        for _ in range(reps):
+            fn()
+        b.record(stream)
+        torch.cuda.synchronize()
+        return a.elapsed_time(b) / reps
+
+    plain = timed(lambda: dvr.render_backward(vol, feats, knots, tf, w.params, sel, T, k, dout))
+    res = {}
+
+    def with_feat():
+        res["r"] = dvr.render_backward(vol, feats, knots, tf, w.params, sel, T, k, dout, want_features=True)
+
+    fgt = timed(with_feat)
+    fg = res["r"][2]
+    fb = timed(lambda: dvr.features_backward(vol, w.spacing, w.sigmas, fg, dvol=dvol, c=w.c, ws=wsb))
+    N = vol.numel()
+    # compulsory bytes of the feature-pass adjoint: read I (4) and dL/d(g, k, V) (20), read and write dL/dI (8)
+    out = {"render_bwd_ms_per_view": plain / len(sel), "render_bwd_feature_grads_ms_per_view": fgt / len(sel),
+           "features_backward_ms": fb, "features_backward_voxels_per_s": N / (fb * 1e-3),
+           "features_backward_hbm_frac": 32.0 * N / (fb * 1e-3) / 8e12, "workspace_bytes": nfb,
+           "workload": f"head {tuple(vol.shape)} FP32 split layout, sigma {{1,2,3}} mm, {len(sel)} views 1024^2"}
+    log(f"render adjoint {out['render_bwd_ms_per_view']:.3f} ms/view, with feature gradients "
+        f"{out['render_bwd_feature_grads_ms_per_view']:.3f} ms/view; feature-pass adjoint {fb:.2f} ms")
+    return out
 
 
 def leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log):

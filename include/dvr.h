@@ -268,7 +268,8 @@ dvr_status dvr_render_backward_features(const void *vol, int32_t vol_dtype, cons
                                         const float *dL_drgba, float *dL_dtf, float *dL_dvol,
                                         const dvr_feature_grads *fg, hipStream_t stream);
 
-/* Workspace of dvr_features_backward in bytes (about 81 bytes per voxel plus the band tables). */
+/* Workspace of dvr_features_backward in bytes (about 57 + 24 nsigma bytes per voxel plus the band
+ * tables). */
 dvr_status dvr_features_backward_workspace(const dvr_grid *grid, const dvr_feature_params *fp, size_t *bytes);
 
 /* Adjoint of dvr_features: adds to dL_dvol the gradient with respect to the voxel intensities I of

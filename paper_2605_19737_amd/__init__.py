@@ -231,6 +231,13 @@ def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_l
     return dtf, dvol, dict(g=dfeat[:3], kappa=dfeat[3], V=dfeat[4], gmax=dgmax, packed=dfeat)
 
 
+def features_backward_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1):
+    n = C.c_size_t()
+    abi.check(lib().dvr_features_backward_workspace(C.byref(grid_struct(shape_zyx, spacing)),
+                                                    C.byref(_fparams(sigmas, alpha, beta, c, 0.0)), C.byref(n)))
+    return n.value
+
+
 def features_backward(vol, spacing, sigmas, fgrads, dvol=None, alpha=0.5, beta=0.5, c=0.1, ws=None):
     """dvr_features_backward: adds dL/dI of the feature pass for the upstream fgrads (the dict that
     render_backward(..., want_features=True) returns, or g [3][...], kappa, V, gmax [1] tensors) to

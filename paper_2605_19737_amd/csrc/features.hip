@@ -225,6 +225,10 @@ hipError_t launch_hessian(const void *vol, int vol_dt, const dvr_grid &g, const 
     a.nz = g.nz;
     a.first = 0;
     a.fro_pass = 0;
+    const int R = taps.ax[0].R;
+    if (R == taps.ax[1].R && R >= kRFastMin && R <= kRFastMax)
+        return (vol_dt == DVR_F32) ? launch_xy_r<DVR_F32, DVR_F32, kHessianOut, kRFastMin>(a, taps, st)
+                                   : launch_xy_r<DVR_F16, DVR_F32, kHessianOut, kRFastMin>(a, taps, st);
     if (vol_dt == DVR_F32) return launch_xy<DVR_F32, DVR_F32, kHessianOut>(a, taps, st);
     return launch_xy<DVR_F16, DVR_F32, kHessianOut>(a, taps, st);
 }

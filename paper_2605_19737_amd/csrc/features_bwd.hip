@@ -6,17 +6,18 @@
 // Every linear step of the forward is a per-axis banded matrix: the clamped central difference of
 // the gradient, and per scale and axis the three combined smoothing-and-difference operators
 // (G, D1 G, D2 G) with their one-sided first and last rows.  The adjoint applies the transposes.
-// Per scale:
-//   1. the six Hessian entries are recomputed with the forward's own kernels (Hessian-output mode);
-//   2. k_fb_local (FP64, one lane per voxel) forms dL/dH: the curvature term g g^T / g^T g at the
+// First the six Hessian entries of every scale are computed with the forward's own kernels
+// (Hessian-output mode) and kept, and the winning scale of each voxel is found (k_fb_win: FP64
+// eigenvalues and V per scale, the first scale whose V exceeds every earlier one and 0).  Then per
+// scale:
+//   1. k_fb_local (FP64, one lane per voxel) forms dL/dH: the curvature term g g^T / g^T g at the
 //      first scale, and at the voxel's winning scale dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T from
 //      a Jacobi eigen-decomposition; at the first scale it also writes dL/dg + dL/dk dk/dg and
 //      the arg-max key of |g|;
-//   3. k_tx, k_ty, k_tz apply the transposed x, y and z operators (the forward's z-then-y-then-x
+//   2. k_tx, k_ty, k_tz apply the transposed x, y and z operators (the forward's z-then-y-then-x
 //      order reversed: six fields after x, three after y, one accumulated into dL/dI after z).
-// The winning scale of each voxel is found first (k_fb_win: FP64 eigenvalues and V per scale, the
-// first scale whose V exceeds every earlier one and 0).  Last, dL/d|g|_max goes to the arg-max voxel's
-// gradient (k_fb_gmax) and the transposed central difference of the gradient is added (k_fb_gradT).
+// Last, dL/d|g|_max goes to the arg-max voxel's gradient (k_fb_gmax) and the transposed central
+// difference of the gradient is added (k_fb_gradT).
 //
 // The band tables are built on the device from the forward's FP32 taps (k_band), so the transpose
 // is that of the operator the forward applies.
@@ -29,36 +30,34 @@ namespace dvr {
 
 // B[f][i][d + R]: weight of input i + d in output i of operator f (0: G, 1: D1 G, 2: D2 G) along an
 // axis of n voxels; clamped taps fold onto the end voxels, the first and last rows are one-sided.
-__global__ __launch_bounds__(256) void k_band(AxisTaps t, int n, float *__restrict__ B)
+// One lane per entry (f, i, d), summing the taps m that land on column i + d; blockIdx.y = axis.
+struct BandJob {
+    AxisTaps t[3];
+    int n[3];
+    float *B[3];
+};
+
+__global__ __launch_bounds__(256) void k_band(BandJob j)
 {
-    const int i = (int)(blockIdx.x * 256u + threadIdx.x);
-    if (i >= n) return;
-    const int R = t.R, W = 2 * R + 1;
+    const int a = (int)blockIdx.y;
+    const AxisTaps &t = j.t[a];
+    const int n = j.n[a], R = t.R, W = 2 * R + 1;
+    const int id = (int)(blockIdx.x * 256u + threadIdx.x);
+    if (id >= 3 * n * W) return;
+    const int f = id / (n * W), rem = id - f * n * W, i = rem / W, d = rem - i * W;
     const int cls = (i == 0) ? 1 : (i == n - 1 ? 2 : 0);
-    float *b0 = B + (size_t)i * W, *b1 = B + ((size_t)n + i) * W, *b2 = B + ((size_t)2 * n + i) * W;
-    for (int d = 0; d < W; ++d) {
-        b0[d] = 0.f;
-        b1[d] = 0.f;
-        b2[d] = 0.f;
-    }
+    float acc = 0.f;
     for (int m = -R; m <= R; ++m) {
+        if (clampi(i + m, 0, n - 1) - i + R != d) continue;
         const int am = m < 0 ? -m : m;
-        const int d = clampi(i + m, 0, n - 1) - i + R;
-        float c1, c2;
-        if (cls == 0) {
-            c1 = m > 0 ? t.D1[am] : (m < 0 ? -t.D1[am] : 0.f);
-            c2 = t.D2[am];
-        } else if (cls == 1) {
-            c1 = t.E1[m + R];
-            c2 = t.E2[m + R];
-        } else {
-            c1 = t.E1[m + 1 + R];
-            c2 = -t.E2[m + 1 + R];
-        }
-        b0[d] += t.G[am];
-        b1[d] += c1;
-        b2[d] += c2;
+        float c;
+        if (f == 0) c = t.G[am];
+        else if (cls == 0) c = (f == 1) ? (m > 0 ? t.D1[am] : (m < 0 ? -t.D1[am] : 0.f)) : t.D2[am];
+        else if (cls == 1) c = (f == 1) ? t.E1[m + R] : t.E2[m + R];
+        else c = (f == 1) ? t.E1[m + 1 + R] : -t.E2[m + 1 + R];
+        acc += c;
     }
+    j.B[a][id] = acc;
 }
 
 template <int DT>
@@ -428,7 +427,7 @@ static size_t al256(size_t b) { return (b + 255u) & ~(size_t)255u; }
 struct BwdWs {
     unsigned long long *key;
     float *zws;   // 3N: z-filtered fields of the Hessian recomputation; then Y (3N)
-    float *H;     // 6N: H of the current scale; then X (6N)
+    float *H;     // 6N per scale: H of every scale; a scale's block then holds X (6N)
     float *Hb;    // 6N: dL/dH of the current scale
     float *dgt;   // 3N: dL/dg total
     double *best; // N
@@ -456,7 +455,7 @@ static BwdWs carve(void *ws, const dvr_grid &g, const FeatBwdPlan &p, size_t *to
     w.zws = (float *)(b + o);
     o += al256(12 * N);
     w.H = (float *)(b + o);
-    o += al256(24 * N);
+    o += al256(24 * N * (size_t)p.nsigma);
     w.Hb = (float *)(b + o);
     o += al256(24 * N);
     w.dgt = (float *)(b + o);
@@ -488,37 +487,46 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     const dim3 pgrid((plane + 255) / 256, g.nz);
     const dim3 vgrid((N + 255) / 256);
     hipError_t e;
-    // band tables of every scale and axis
+    // band tables of every scale and axis (one launch per scale)
     float *bt[DVR_MAX_SIGMA][3];
     {
         float *b = w.band;
-        for (int s = 0; s < p.nsigma; ++s)
+        for (int s = 0; s < p.nsigma; ++s) {
+            BandJob j;
+            int most = 0;
             for (int a = 0; a < 3; ++a) {
                 bt[s][a] = b;
-                hipLaunchKernelGGL(k_band, dim3((n[a] + 255) / 256), dim3(256), 0, st, p.taps[s].ax[a], n[a], b);
-                b += (size_t)3 * n[a] * (2 * p.taps[s].ax[a].R + 1);
+                j.t[a] = p.taps[s].ax[a];
+                j.n[a] = n[a];
+                j.B[a] = b;
+                const int cnt = 3 * n[a] * (2 * p.taps[s].ax[a].R + 1);
+                most = cnt > most ? cnt : most;
+                b += cnt;
             }
+            hipLaunchKernelGGL(k_band, dim3((most + 255) / 256, 3), dim3(256), 0, st, j);
+        }
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     hipLaunchKernelGGL(k_zero_u64, dim3(1), dim3(64), 0, st, w.key);
-    // winning scale of each voxel
+    // every scale's Hessian, and the winning scale of each voxel
     for (int s = 0; s < p.nsigma; ++s) {
-        if ((e = launch_hessian(vol, vol_dt, g, p.taps[s], w.zws, w.H, st)) != hipSuccess) return e;
-        hipLaunchKernelGGL(k_fb_win, vgrid, dim3(256), 0, st, w.H, w.best, w.win, s, p.sigma2[s], p.inv2a2, p.inv2b2,
+        float *Hs = w.H + (size_t)6 * N * s;
+        if ((e = launch_hessian(vol, vol_dt, g, p.taps[s], w.zws, Hs, st)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_fb_win, vgrid, dim3(256), 0, st, Hs, w.best, w.win, s, p.sigma2[s], p.inv2a2, p.inv2b2,
                            p.inv2c2, N);
     }
     if ((e = hipGetLastError()) != hipSuccess) return e;
     for (int s = 0; s < p.nsigma; ++s) {
-        if ((e = launch_hessian(vol, vol_dt, g, p.taps[s], w.zws, w.H, st)) != hipSuccess) return e;
+        float *Hs = w.H + (size_t)6 * N * s;
         if (vol_dt == DVR_F32)
-            hipLaunchKernelGGL(k_fb_local<DVR_F32>, pgrid, dim3(256), 0, st, vol, w.H, dfeat, w.win, w.Hb, w.dgt, w.key,
+            hipLaunchKernelGGL(k_fb_local<DVR_F32>, pgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
                                s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
                                p.inv2h[2]);
         else
-            hipLaunchKernelGGL(k_fb_local<DVR_F16>, pgrid, dim3(256), 0, st, vol, w.H, dfeat, w.win, w.Hb, w.dgt, w.key,
+            hipLaunchKernelGGL(k_fb_local<DVR_F16>, pgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
                                s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
                                p.inv2h[2]);
-        float *X = w.H, *Y = w.zws;
+        float *X = Hs, *Y = w.zws;  // this scale's H is no longer needed
         hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
         hipLaunchKernelGGL(k_ty, pgrid, dim3(256), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
         hipLaunchKernelGGL(k_tz, pgrid, dim3(256), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
