@@ -49,6 +49,13 @@ __device__ __forceinline__ u32x4 ld4(Buf b, uint32_t byte_off)
     return __builtin_amdgcn_raw_buffer_load_b128(b.r, byte_off, 0, 0);
 }
 
+typedef float f32x2 __attribute__((ext_vector_type(2)));
+// two consecutive floats (byte_off 4-byte aligned; both must lie inside the buffer)
+__device__ __forceinline__ f32x2 ld2f(Buf b, uint32_t byte_off)
+{
+    return __builtin_bit_cast(f32x2, __builtin_amdgcn_raw_buffer_load_b64(b.r, byte_off, 0, 0));
+}
+
 // Load one element of a volume stored as F32 or F16.
 template <int DT>
 __device__ __forceinline__ float ldv(Buf b, uint32_t idx)

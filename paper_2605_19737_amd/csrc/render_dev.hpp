@@ -257,6 +257,17 @@ struct CornerCache {
     {
         if (c.off[0] == base) return;
         base = c.off[0];
+        if constexpr (LAYOUT != DVR_INTERLEAVED && DT == DVR_F32) {
+            // corners x and x + 1 are adjacent floats: one 8-byte load per (y, z) row of the cell
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const f32x2 p = ld2f(vx.b[0], c.off[j]);
+                v[2 * j][0] = p.x;
+                v[2 * j + 1][0] = p.y;
+            }
+            feat = false;
+            return;
+        }
 #pragma unroll
         for (int e = 0; e < 8; ++e) {
             const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
@@ -286,7 +297,18 @@ struct CornerCache {
 
     __device__ __forceinline__ void need_feat(const Vox<LAYOUT, DT> &vx, const Corners &c)
     {
-        if constexpr (LAYOUT == DVR_PLANAR) {
+        if constexpr (LAYOUT == DVR_PLANAR && DT == DVR_F32) {
+            if (feat) return;
+            feat = true;
+#pragma unroll
+            for (int j = 0; j < 4; ++j)
+#pragma unroll
+                for (int ch = 1; ch < 6; ++ch) {
+                    const f32x2 p = ld2f(vx.b[ch], c.off[j]);
+                    v[2 * j][ch] = p.x;
+                    v[2 * j + 1][ch] = p.y;
+                }
+        } else if constexpr (LAYOUT == DVR_PLANAR) {
             if (feat) return;
             feat = true;
 #pragma unroll
@@ -310,7 +332,11 @@ struct CornerCache {
                     v[e][2] = r.y;
                     v[e][3] = r.z;
                     v[e][4] = r.w;
-                    v[e][5] = ldf(vx.b[2], off);
+                    if ((e & 1) == 0) {  // V of corners x and x + 1 in one 8-byte load
+                        const f32x2 p = ld2f(vx.b[2], off);
+                        v[e][5] = p.x;
+                        v[e + 1][5] = p.y;
+                    }
                 } else {
                     const f16x4 r = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(vx.b[1].r, off << 2, 0, 0));
                     v[e][1] = (float)r.x;
