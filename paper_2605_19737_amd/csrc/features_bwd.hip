@@ -28,9 +28,11 @@
 
 namespace dvr {
 
-// B[f][i][d + R]: weight of input i + d in output i of operator f (0: G, 1: D1 G, 2: D2 G) along an
+// B[f][d + R][i]: weight of input i + d in output i of operator f (0: G, 1: D1 G, 2: D2 G) along an
 // axis of n voxels; clamped taps fold onto the end voxels, the first and last rows are one-sided.
-// One lane per entry (f, i, d), summing the taps m that land on column i + d; blockIdx.y = axis.
+// Stored d-major so that lanes on consecutive outputs of a transposed filter read consecutive
+// entries.  One lane per entry (f, d, i), summing the taps m that land on column i + d;
+// blockIdx.y = axis.
 struct BandJob {
     AxisTaps t[3];
     int n[3];
@@ -44,7 +46,7 @@ __global__ __launch_bounds__(256) void k_band(BandJob j)
     const int n = j.n[a], R = t.R, W = 2 * R + 1;
     const int id = (int)(blockIdx.x * 256u + threadIdx.x);
     if (id >= 3 * n * W) return;
-    const int f = id / (n * W), rem = id - f * n * W, i = rem / W, d = rem - i * W;
+    const int f = id / (n * W), rem = id - f * n * W, d = rem / n, i = rem - d * n;
     const int cls = (i == 0) ? 1 : (i == n - 1 ? 2 : 0);
     float acc = 0.f;
     for (int m = -R; m <= R; ++m) {
@@ -292,7 +294,7 @@ __global__ __launch_bounds__(256) void k_tx(const float *__restrict__ Hb, float 
     const int i0 = max(0, x - R), i1 = min(nx - 1, x + R);
     for (int i = i0; i <= i1; ++i) {
         const int d = x - i + R;
-        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)nx + i) * W + d], b2 = B[((size_t)2 * nx + i) * W + d];
+        const float b0 = B[(size_t)d * nx + i], b1 = B[(size_t)(W + d) * nx + i], b2 = B[(size_t)(2 * W + d) * nx + i];
         const size_t sidx = row + i;
         acc[0] = fmaf(b2, Hb[sidx], acc[0]);
         acc[1] = fmaf(b0, Hb[N + sidx], acc[1]);
@@ -322,7 +324,7 @@ __global__ __launch_bounds__(256) void k_ty(const float *__restrict__ X, float *
     const int i0 = max(0, y - R), i1 = min(ny - 1, y + R);
     for (int i = i0; i <= i1; ++i) {
         const int d = y - i + R;
-        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)ny + i) * W + d], b2 = B[((size_t)2 * ny + i) * W + d];
+        const float b0 = B[(size_t)d * ny + i], b1 = B[(size_t)(W + d) * ny + i], b2 = B[(size_t)(2 * W + d) * ny + i];
         const size_t sidx = col + (size_t)i * nx;
         y0 = fmaf(b0, X[sidx], y0);
         y0 = fmaf(b2, X[N + sidx], y0);
@@ -351,7 +353,7 @@ __global__ __launch_bounds__(256) void k_tz(const float *__restrict__ Y, float *
     const int i0 = max(0, z - R), i1 = min(nz - 1, z + R);
     for (int i = i0; i <= i1; ++i) {
         const int d = z - i + R;
-        const float b0 = B[(size_t)i * W + d], b1 = B[((size_t)nz + i) * W + d], b2 = B[((size_t)2 * nz + i) * W + d];
+        const float b0 = B[(size_t)d * nz + i], b1 = B[(size_t)(W + d) * nz + i], b2 = B[(size_t)(2 * W + d) * nz + i];
         const size_t sidx = (size_t)i * plane + e;
         acc = fmaf(b0, Y[sidx], acc);
         acc = fmaf(b1, Y[N + sidx], acc);
