@@ -608,7 +608,8 @@ struct DWinT {
     static constexpr int kVox = W0 * W1 * W2;      // voxels of the window
     static constexpr int kEntries = kVox * CH;     // doubles in LDS
     static_assert(kVox % 64 == 0, "whole flush rounds");
-    double *w;    // this wave's kEntries in LDS: [voxel u0 + W0 (u1 + W1 u2)][channel]
+    double *w;    // this wave's kEntries in LDS: [channel][voxel u0 + W0 (u1 + W1 u2)] (channel-major:
+                  // lanes on neighbouring voxels of one channel fall in different banks)
     int o[3];     // voxel index (x, y, z) of the window's first entry; wave-uniform
     int ext[3];   // window extent along voxel axis x, y, z
     int st[3];    // window index stride of voxel axis x, y, z
@@ -656,10 +657,10 @@ struct DWinT {
             const int gi = olin + u0 * gst[0] + u1 * gst[1] + u2 * gst[2];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const double v = w[e * CH + c];
+                const double v = w[c * kVox + e];
                 if (v != 0.0) {
                     atomicAdd(c == 0 ? dvol + gi : dfeat + (size_t)(c - 1) * N + gi, (float)v);
-                    w[e * CH + c] = 0.0;
+                    w[c * kVox + e] = 0.0;
                 }
             }
         }
@@ -772,11 +773,11 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 const int b = dw.index(acell);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    double *p = win + (b + dw.crn[e]) * 6;
+                    double *p = win + (b + dw.crn[e]);
 #pragma unroll
                     for (int ch6 = 0; ch6 < 6; ++ch6)
                         if (acc[e * 6 + ch6] != 0.f)
-                            __hip_atomic_fetch_add(p + ch6, (double)acc[e * 6 + ch6], __ATOMIC_RELAXED,
+                            __hip_atomic_fetch_add(p + ch6 * DWinF::kVox, (double)acc[e * 6 + ch6], __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
             } else if (flag) {
