@@ -122,8 +122,18 @@ def hessian_T(Hb, spacing, sigma_mm, ops=None):
 
 
 def gradient(I, spacing):
-    n = _shape_n(I.shape)
-    return np.stack([apply(d1_matrix(n[a], spacing[a]), I, a) for a in range(3)])
+    """Eq. 2 as the difference quotient of the clamped neighbours (the same linear map as D1_a, but
+    exactly 0 where the two neighbours are equal, which R5's k = 0 at g = 0 relies on; a matrix
+    product can leave a rounding residual there)."""
+    g = []
+    for a in range(3):
+        ax = AX[a]
+        n = I.shape[ax]
+        idx = np.arange(n)
+        up = np.take(I, np.minimum(idx + 1, n - 1), axis=ax)
+        dn = np.take(I, np.maximum(idx - 1, 0), axis=ax)
+        g.append((up - dn) / (2.0 * spacing[a]))
+    return np.stack(g)
 
 
 def gradient_T(gb, spacing):

@@ -102,6 +102,9 @@ def _vessel_crop(shape, seed):
     ((40, 70, 90), (0.9, 0.9, 1.2), [1.0, 2.0, 3.0], torch.float32),
     ((17, 19, 66), (0.7, 1.1, 2.5), [0.8], torch.float16),
     ((2, 3, 5), (1.0, 1.0, 1.0), [1.0, 1.5], torch.float32),
+    ((2, 2, 2), (1.0, 1.0, 1.0), [1.0, 1.5], torch.float32),
+    # eight scales (the most the ABI takes); radii up to 12 take the generic Hessian kernels
+    ((9, 12, 70), (0.8, 0.8, 1.1), [0.6, 0.8, 1.0, 1.3, 1.6, 2.0, 2.4, 2.8], torch.float32),
 ])
 def test_feature_adjoint_matches_oracle(shape, spacing, sigmas, dtype):
     print(f"[feature adjoint] shape={shape} spacing={spacing} sigmas={sigmas} dtype={dtype}", flush=True)
@@ -172,3 +175,24 @@ def test_end_to_end_gradient():
           f"near-tie voxels {ties}, near-knot voxels {int((~keep).sum())})", flush=True)
     assert np.linalg.norm(rfeat) > 0.05 * np.linalg.norm(rI)
     assert e <= 1e-4
+
+
+def test_feature_adjoint_flat_volume():
+    """A constant volume: g = 0, k = 0, V = 0 and gmax = 0 everywhere, so only the transposed
+    gradient of dL/dg remains (no curvature, vesselness or gmax term), against the oracle."""
+    shape = (11, 13, 17)
+    I = np.full(shape, 0.37)
+    dv = to_dev(I)
+    rng = np.random.default_rng(8)
+    gb, kb, Vb = rng.normal(size=(3,) + shape), rng.normal(size=shape), rng.normal(size=shape)
+    fg = dict(g=to_dev(gb), kappa=to_dev(kb), V=to_dev(Vb), gmax=torch.tensor([0.9], dtype=torch.float32, device="cuda"))
+    sp = (1.0, 0.9, 1.2)
+    d = dvr.features_backward(dv, sp, [1.0, 2.0], fg, c=0.1).cpu().numpy()
+    I64 = dv.cpu().numpy().astype(np.float64)
+    r = fa.vjp(I64, sp32(sp), [1.0, 2.0], 0.5, 0.5, f32(0.1), np.float32(gb).astype(np.float64),
+               np.float32(kb).astype(np.float64), np.float32(Vb).astype(np.float64), float(np.float32(0.9)))
+    only_g = fa.gradient_T(np.float32(gb).astype(np.float64), sp32(sp))
+    np.testing.assert_allclose(r, only_g, rtol=0, atol=1e-12)
+    e = _nerr(d, r)
+    print(f"[feature adjoint] flat volume err={e:.2e}", flush=True)
+    assert e <= 1e-5
