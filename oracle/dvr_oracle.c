@@ -509,12 +509,16 @@ int oracle_render(const double *I, const double *g, const double *kap, const dou
 /* the plain adjoints of C += T a c and T' = T exp(-x); x = tau M delta with M = m w u gives      */
 /* dL/dM = dL/dx tau delta, and the chain rule through m (|g| / gmax, inactive where clamped at 1),*/
 /* w (|k| / (|k| + k0), derivative 0 at k = 0) and u (1 + lambda_v V).  All outputs overwritten.   */
+/* near_knot (nullable, [N] bytes, test support): set to 1 at the 8 corners of every sample whose  */
+/* intensity lies within knot_eps of a TF knot (the TF slope jumps there, so a lower-precision     */
+/* evaluation may take the neighbouring segment), 0 elsewhere.                                     */
 int oracle_render_vjp(const double *I, const double *g, const double *kap, const double *ves,
                       int nx, int ny, int nz, double hx, double hy, double hz, double gmax,
                       int K, const double *knots, const double *rgba, const double *prm,
                       const double *cams, int ncam, const int32_t *pix, int64_t npix,
                       const double *dout, double *dL_dtf, double *dL_dI,
-                      double *dL_dg, double *dL_dkap, double *dL_dves, double *dL_dgmax)
+                      double *dL_dg, double *dL_dkap, double *dL_dves, double *dL_dgmax,
+                      double knot_eps, uint8_t *near_knot)
 {
     if (nx < 2 || ny < 2 || nz < 2 || K < 2) return -1;
     scene_t sc;
@@ -525,6 +529,7 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
     if (dL_dg) for (int64_t v = 0; v < 3 * N; ++v) dL_dg[v] = 0.0;
     if (dL_dkap) for (int64_t v = 0; v < N; ++v) dL_dkap[v] = 0.0;
     if (dL_dves) for (int64_t v = 0; v < N; ++v) dL_dves[v] = 0.0;
+    if (near_knot) for (int64_t v = 0; v < N; ++v) near_knot[v] = 0;
     double gmax_acc = 0.0;
     const int want_feat = dL_dg || dL_dkap || dL_dves || dL_dgmax;
     int err = 0;
@@ -568,6 +573,17 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
                         tfacc[4 * s->seg + ch] += (1.0 - s->t) * vbar[ch];
                         tfacc[4 * (s->seg + 1) + ch] += s->t * vbar[ch];
                     }
+                }
+                if (near_knot) {
+                    double I = 0.0;
+                    for (int c8 = 0; c8 < 8; ++c8) I += s->cn.w[c8] * sc.I[s->cn.idx[c8]];
+                    int near = 0;
+                    for (int kk = 0; kk < K; ++kk) near |= fabs(I - knots[kk]) < knot_eps;
+                    if (near)
+                        for (int c8 = 0; c8 < 8; ++c8) {
+#pragma omp atomic write
+                            near_knot[s->cn.idx[c8]] = 1;
+                        }
                 }
                 if (want_feat) {
                     /* x = tau M dk */

@@ -163,3 +163,15 @@ def test_end_to_end_gradient_through_the_features():
         dirn = rng.normal(size=vol.shape)
         fd = (L(vol + eps * dirn) - L(vol - eps * dirn)) / (2 * eps)
         assert abs(fd - (dI * dirn).sum()) <= 1e-5 * abs(fd)
+
+
+def test_near_knot_mask_matches_brute_force():
+    """The oracle's near-knot corner mask (the tolerated set of dL/dI comparisons) equals the one
+    found by brute force (face-clipped rays, map_coordinates samples)."""
+    from tests import bruteforce as bf
+    vol, f, sp, knots, rgba, prm, cams, dout = _render_setup(41)
+    eps = 2e-2  # wide, so that the mask is not empty on this small scene
+    *_, mask = oracle.render_vjp(vol, f, f["gmax"], sp, knots, rgba, prm, cams, dout, near_knot_eps=eps)
+    ref = bf.near_knot_voxels(vol.shape, sp, vol, knots, prm, cams, eps=eps)
+    assert mask.any() and not mask.all()
+    np.testing.assert_array_equal(mask, ref)
