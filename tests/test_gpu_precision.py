@@ -135,3 +135,66 @@ def test_c5_render_and_adjoint_fp16(c5):
     # stated FP16-mode image bound (input quantization 2^-12 of I through TF slopes up to ~33 per unit
     # I, storage 2^-11 of g, k, V): measured 5.4e-4 of the range, 1.2e-5 mean; guard at 2e-3 / 1e-4
     assert max(ec) <= 2e-3 and mean <= 1e-4
+
+
+def test_c5_tissue_windows_full_size(c5):
+    """f1 at full size: the 256-bin histogram of the normalized FP16 volume bit-exact against the
+    oracle on the same values, and the same three peaks."""
+    import oracle.tissue as ot
+    w, raw, v16, _ = c5
+    h, used = dvr.histogram(v16, 0.0)
+    vals = v16.float().cpu().numpy()
+    ref, ref_used = ot.histogram(vals, 0.0)
+    np.testing.assert_array_equal(h.cpu().numpy(), ref)
+    assert used == ref_used
+    _, pk = dvr.tissue_peaks(h, 2)
+    rp = ot.tissue_peaks(ref, 2)
+    print(f"[c5] histogram of {vals.size} voxels exact; peaks {pk['bin']} (oracle {rp['bin']})", flush=True)
+    assert pk["bin"] == rp["bin"] and pk["in_window"] == rp["in_window"]
+
+
+def test_c5_denoise_full_size(c5):
+    """f4 at full size: the 3x3x3 median bit-exact at sampled voxels (brute force on the same FP16
+    values, faces and corners included) and the separable Gaussian within one FP16 ulp of the FP64
+    oracle on every voxel."""
+    import oracle.denoise as od
+    w, raw, v16, _ = c5
+    vals = v16.float().cpu().numpy()
+    med = dvr.denoise(v16, w.spacing, "median3").float().cpu().numpy()
+    nz, ny, nx = vals.shape
+    rng = np.random.default_rng(5)
+    pts = [tuple(rng.integers(0, n) for n in vals.shape) for _ in range(400)]
+    pts += [(0, 0, 0), (nz - 1, ny - 1, nx - 1), (0, ny - 1, 7), (nz // 2, 0, nx - 1), (3, ny // 2, 0)]
+    for (z, y, x) in pts:
+        nb = [vals[min(max(z + a, 0), nz - 1), min(max(y + b, 0), ny - 1), min(max(x + c, 0), nx - 1)]
+              for a in (-1, 0, 1) for b in (-1, 0, 1) for c in (-1, 0, 1)]
+        assert med[z, y, x] == sorted(nb)[13], (z, y, x)
+    del med
+    g = dvr.denoise(v16, w.spacing, "gauss", 1.0).float().cpu().numpy().astype(np.float64)
+    ref = od.gauss(vals, sp32(w.spacing), 1.0)
+    r16 = ref.astype(np.float16).astype(np.float64)
+    ulp = np.spacing(np.abs(r16).astype(np.float16)).astype(np.float64)
+    bad = int((np.abs(g - r16) > ulp).sum())
+    print(f"[c5] median exact at {len(pts)} voxels; Gaussian: max |gpu - fp16(oracle)| {np.abs(g - r16).max():.3e}, "
+          f"beyond 1 ulp {bad}", flush=True)
+    assert bad == 0
+
+
+def test_c5_skipping_bit_exact_full_size(c5):
+    """f3 at full size: two 2048^2 views of the FP16 records with and without the brick table give
+    the same bits (image, ray state, sample counts), and the table does skip bricks."""
+    w, raw, v16, f = c5
+    assert f.bricks is not None
+    kn = torch.from_numpy(w.tf_knots).cuda()
+    tf = torch.from_numpy(w.tf_rgba).cuda()
+    outs = []
+    for ff in (f, f.without_bricks()):
+        cnt = torch.zeros(2, dtype=torch.int64, device="cuda")
+        img, T, k = dvr.render(None, ff, kn, tf, w.params, w.cams[:2], counters=cnt)
+        torch.cuda.synchronize()
+        outs.append((img.cpu().numpy(), T.cpu().numpy(), k.cpu().numpy(), cnt.cpu().numpy()))
+    for a, b in zip(*outs):
+        np.testing.assert_array_equal(a, b)
+    mm = f.brick_minmax().cpu().numpy()
+    print(f"[c5] skipping bit-exact on 2 views 2048^2; bricks with max below the first non-zero knot: "
+          f"{(mm[..., 1] < float(w.tf_knots[1])).mean():.2f}", flush=True)
