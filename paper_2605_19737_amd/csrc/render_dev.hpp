@@ -109,6 +109,7 @@ struct TFShared {
     float x[KMAX];
     float iw[KMAX];
     int nzp[KMAX + 2];
+    int K;
 };
 
 template <int KMAX>
@@ -133,6 +134,7 @@ __device__ __forceinline__ void tf_load(TFShared<KMAX> &sh, float (&kx)[KMAX], c
         }
     }
     if (threadIdx.x == 0) {
+        sh.K = K;
         const float4 *r = reinterpret_cast<const float4 *>(tf.rgba);
         int c = 0;
         sh.nzp[0] = 0;
@@ -441,6 +443,10 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
         if (skip) bm = make_buf(feat.bricks + 2 * nbt, (uint32_t)((nbt + 31) / 32) * 4u);
         int cur_brick = -1;
         bool cur_empty = false;
+        // the TF segment of the last full evaluation: [t_lo, t_hi) (empty before the first)
+        float t_lo = INFINITY, t_hi = -INFINITY, t_x = 0.f;
+        float4 t_v = make_float4(0.f, 0.f, 0.f, 0.f), t_s = t_v;
+        bool t_below = false;
         for (int k = 0; k < r.N; ++k) {
             if (skip) {
                 const int bi = ((int)(q[2] >> 34) * feat.nb[1] + (int)(q[1] >> 34)) * feat.nb[0] + (int)(q[0] >> 34);
@@ -468,7 +474,24 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
             cc.need_I(vx, c);
             ch.I = cc.interp(c, 0);
             Opt o;
-            tf_eval<KMAX>(sh, kx, ch.I, o);
+            if (ch.I >= t_lo && ch.I < t_hi) {
+                // same TF segment as the previous evaluated sample: the same arithmetic as tf_eval
+                // on the kept segment values, without the knot search and the LDS reads
+                const float dI = t_below ? 0.f : ch.I - t_x;
+                o.c[0] = fmaf(dI, t_s.x, t_v.x);
+                o.c[1] = fmaf(dI, t_s.y, t_v.y);
+                o.c[2] = fmaf(dI, t_s.z, t_v.z);
+                o.tau = fmaf(dI, t_s.w, t_v.w);
+            } else {
+                tf_eval<KMAX>(sh, kx, ch.I, o);
+                t_below = o.seg < 0;
+                const int sg = t_below ? 0 : o.seg;
+                t_x = sh.x[sg];
+                t_v = sh.v[sg];
+                t_s = sh.s[sg];
+                t_lo = t_below ? -INFINITY : t_x;
+                t_hi = t_below ? t_x : (sg + 1 < sh.K ? sh.x[sg + 1] : INFINITY);
+            }
             Tprev = T;
             if (o.tau > 0.f) {
                 ++shaded;
