@@ -36,11 +36,18 @@ def _diff_scene(n=48):
     return w
 
 
-@pytest.mark.parametrize("layout,dtype", [(abi.DVR_PLANAR, torch.float32), (abi.DVR_SPLIT, torch.float32),
-                                          (abi.DVR_INTERLEAVED, torch.float16), (abi.DVR_SPLIT, torch.float16)])
-def test_render_feature_grads_match_oracle(layout, dtype):
+@pytest.mark.parametrize("layout,dtype,K", [(abi.DVR_PLANAR, torch.float32, 16), (abi.DVR_SPLIT, torch.float32, 16),
+                                            (abi.DVR_INTERLEAVED, torch.float16, 16), (abi.DVR_SPLIT, torch.float16, 16),
+                                            (abi.DVR_PLANAR, torch.float16, 16), (abi.DVR_SPLIT, torch.float32, 40),
+                                            (abi.DVR_INTERLEAVED, torch.float32, 6)])
+def test_render_feature_grads_match_oracle(layout, dtype, K):
     w = _diff_scene()
-    print(f"[render feature grads] layout={layout} dtype={dtype}", flush=True)
+    if K != len(w.tf_knots):
+        # a TF with K knots (the K <= 8 and K <= 64 kernel variants)
+        rng = np.random.default_rng(K)
+        w.tf_knots = np.sort(np.concatenate([[0.0, 1.0], rng.uniform(0.02, 0.98, K - 2)])).astype(np.float32)
+        w.tf_rgba = np.concatenate([rng.uniform(0, 1, (K, 3)), rng.uniform(0.0, 0.2, (K, 1))], 1).astype(np.float32)
+    print(f"[render feature grads] layout={layout} dtype={dtype} K={K}", flush=True)
     dv = to_dev(w.vol, dtype)
     f = dvr.features(dv, w.spacing, w.sigmas, c=w.c, dtype=dtype, layout=layout)
     kn, rg = tf_dev(w)
