@@ -472,7 +472,10 @@ def leg_c5(dev, stream, dvr, torch, np, log):
            "normalize_hbm_frac": 6 * raw.numel() / (t[0] / 1e3) / (PEAK_HBM_GBS * 1e9),
            "histogram_ms": th, "histogram_hbm_frac": 2 * raw.numel() / (th / 1e3) / (PEAK_HBM_GBS * 1e9),
            "tissue_peaks": pk,
+           # the median is ALU work: 388 min/max per voxel (forgetful selection over 27 values) against
+           # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 32-bit operations per second
            "median3_ms": tdn, "median3_hbm_frac": 4 * raw.numel() / (tdn / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "median3_alu_frac": 388.0 * raw.numel() / (tdn / 1e3) / 3.93216e13,
            "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9)}
     log(f"C5: normalize {t[0]:.2f} ms, features {t[1]:.2f} ms, fwd {t[2] / 8:.2f} ms/view, bwd {t[3] / 8:.2f} ms/view")
     return out

@@ -1,6 +1,8 @@
 // Automatic tissue windows (Sec. 2.2 "256-bin density analysis" and tissue peaks; Sec. 3.1 Table 2):
 //   k_hist       256-bin counts of a normalized volume, privatized per workgroup in LDS (integer LDS
-//                atomics), one global atomic per non-empty bin per workgroup;
+//                atomics) in kHistCopies interleaved copies (lane mod copies), so that lanes hitting
+//                one bin at once (a volume's background fills one bin) spread over several addresses
+//                and banks; one global atomic per non-empty bin per workgroup;
 //   k_peaks      the three tissue peaks of the [1, 2, 1]-smoothed counts: local maxima taken greedily
 //                by height at least min_sep bins apart, as three workgroup arg-max reductions (the
 //                first is the highest maximum, the next the highest one far enough from those taken,
@@ -11,13 +13,16 @@
 
 namespace dvr {
 
+constexpr int kHistCopies = 8;
+
+// h: this lane's copy, bin b at h[b * kHistCopies]
 template <int DT>
 __device__ __forceinline__ void hist_add(uint32_t *h, float x, float floor_, uint32_t &used)
 {
     if (x > floor_) {
         int b = (int)floorf(x * 256.f);
         b = b < 0 ? 0 : (b > 255 ? 255 : b);
-        atomicAdd(h + b, 1u);
+        atomicAdd(h + b * kHistCopies, 1u);
         ++used;
     }
 }
@@ -26,16 +31,16 @@ template <int DT>
 __global__ __launch_bounds__(256) void k_hist(const void *__restrict__ vol, int64_t n, float floor_, uint32_t *hist,
                                               uint32_t *used_out)
 {
-    __shared__ uint32_t h[256];
+    __shared__ uint32_t hs[256 * kHistCopies];
     __shared__ uint32_t wu[4];
-    h[threadIdx.x] = 0u;
+    for (int i = threadIdx.x; i < 256 * kHistCopies; i += 256) hs[i] = 0u;
     __syncthreads();
+    uint32_t *h = hs + (threadIdx.x % kHistCopies);
     constexpr int K = (DT == DVR_F32) ? 4 : 8;  // values per 16-byte load
     const int64_t nv = n / K;
     const int64_t stride = (int64_t)gridDim.x * blockDim.x;
     uint32_t used = 0u;
-    for (int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; j < nv; j += stride) {
-        const uint4 u = reinterpret_cast<const uint4 *>(vol)[j];
+    auto add16 = [&](const uint4 &u) {
         const uint32_t w[4] = {u.x, u.y, u.z, u.w};
         if constexpr (DT == DVR_F32) {
             for (int e = 0; e < 4; ++e) hist_add<DT>(h, __uint_as_float(w[e]), floor_, used);
@@ -44,7 +49,18 @@ __global__ __launch_bounds__(256) void k_hist(const void *__restrict__ vol, int6
                 hist_add<DT>(h, __half2float(__builtin_bit_cast(__half, (uint16_t)(w[e >> 1] >> ((e & 1) * 16)))), floor_,
                              used);
         }
+    };
+    const uint4 *v4 = reinterpret_cast<const uint4 *>(vol);
+    int64_t j = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    // four 16-byte loads in flight per lane, then their values
+    for (; j + 3 * stride < nv; j += 4 * stride) {
+        const uint4 u0 = v4[j], u1 = v4[j + stride], u2 = v4[j + 2 * stride], u3 = v4[j + 3 * stride];
+        add16(u0);
+        add16(u1);
+        add16(u2);
+        add16(u3);
     }
+    for (; j < nv; j += stride) add16(v4[j]);
     for (int64_t i = nv * K + (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += stride) {
         const float x = (DT == DVR_F32) ? reinterpret_cast<const float *>(vol)[i]
                                         : __half2float(reinterpret_cast<const __half *>(vol)[i]);
@@ -53,7 +69,10 @@ __global__ __launch_bounds__(256) void k_hist(const void *__restrict__ vol, int6
     for (int o = 32; o > 0; o >>= 1) used += __shfl_xor(used, o, 64);
     if ((threadIdx.x & 63) == 0) wu[threadIdx.x >> 6] = used;
     __syncthreads();
-    if (h[threadIdx.x] != 0u) atomicAdd(hist + threadIdx.x, h[threadIdx.x]);
+    uint32_t tot_b = 0u;
+#pragma unroll
+    for (int c = 0; c < kHistCopies; ++c) tot_b += hs[threadIdx.x * kHistCopies + c];
+    if (tot_b != 0u) atomicAdd(hist + threadIdx.x, tot_b);
     if (threadIdx.x == 0 && used_out) {
         const uint32_t tot = wu[0] + wu[1] + wu[2] + wu[3];
         if (tot) atomicAdd(used_out, tot);
@@ -169,7 +188,9 @@ hipError_t launch_histogram(const void *vol, int dt, int64_t n, float floor_, ui
     if (used) hipLaunchKernelGGL(k_zero_u32, dim3(1), dim3(64), 0, st, used, 1);
     const int K = dt == DVR_F32 ? 4 : 8;
     const int64_t b64 = (n / K + 255) / 256;
-    const unsigned blocks = (unsigned)(b64 < 2048 ? (b64 > 0 ? b64 : 1) : 2048);
+    // 1024 workgroups: enough to fill the chip, and each bin's global counter takes one add per
+    // workgroup (same-address atomics serialize at the L2)
+    const unsigned blocks = (unsigned)(b64 < 1024 ? (b64 > 0 ? b64 : 1) : 1024);
     if (dt == DVR_F32)
         hipLaunchKernelGGL(k_hist<DVR_F32>, dim3(blocks), dim3(256), 0, st, vol, n, floor_, hist, used);
     else
