@@ -145,7 +145,7 @@ __device__ __forceinline__ void ray_pixel(int ray_tile, int tiles_x, int tile, i
 }
 
 template <int LAYOUT, int DT, int KMAX, int TXY>
-__global__ __launch_bounds__(256, 4) void k_batch(BatchArgs A)
+__global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
 {
     constexpr int TX = XYShape<TXY>::TX, TY = XYShape<TXY>::TY;
     extern __shared__ float lds[];
