@@ -18,9 +18,10 @@ __device__ __forceinline__ int clampi(int v, int lo, int hi) { return v < lo ? l
 template <typename T>
 __device__ __forceinline__ void eig_trig(T a00, T a11, T a22, T a01, T a02, T a12, T &lmin, T &lmid, T &lmax)
 {
-    const T m = (a00 + a11 + a22) / T(3);
+    // constant divisors as products with their reciprocals (a few ulps, no division sequences)
+    const T m = (a00 + a11 + a22) * T(1.0 / 3.0);
     const T b00 = a00 - m, b11 = a11 - m, b22 = a22 - m;
-    const T p2 = (b00 * b00 + b11 * b11 + b22 * b22 + T(2) * (a01 * a01 + a02 * a02 + a12 * a12)) / T(6);
+    const T p2 = (b00 * b00 + b11 * b11 + b22 * b22 + T(2) * (a01 * a01 + a02 * a02 + a12 * a12)) * T(1.0 / 6.0);
     if (!(p2 > T(0))) {
         lmin = lmid = lmax = m;
         return;
@@ -30,7 +31,7 @@ __device__ __forceinline__ void eig_trig(T a00, T a11, T a22, T a01, T a02, T a1
     const T c00 = b00 * ip, c11 = b11 * ip, c22 = b22 * ip, c01 = a01 * ip, c02 = a02 * ip, c12 = a12 * ip;
     T q = T(0.5) * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02));
     q = q < T(-1) ? T(-1) : (q > T(1) ? T(1) : q);
-    const T phi = acos(q) / T(3);
+    const T phi = acos(q) * T(1.0 / 3.0);
     lmax = m + T(2) * p * cos(phi);
     lmin = m + T(2) * p * cos(phi + T(2.0943951023931954923));
     lmid = (a00 + a11 + a22) - lmax - lmin;
@@ -67,8 +68,9 @@ __device__ __forceinline__ void eig_sorted(const float A[6], float tau, float &l
 __device__ __forceinline__ float frangi(float l1, float l2, float l3, float inv2a2, float inv2b2, float inv2c2)
 {
     if (l2 >= 0.f || l3 >= 0.f) return 0.f;
-    const float Ra2 = (l2 * l2) / (l3 * l3);
-    const float Rb2 = (l1 * l1) / fabsf(l2 * l3);
+    // quotients through the hardware reciprocal (1 ulp) instead of IEEE division sequences
+    const float Ra2 = (l2 * l2) * __builtin_amdgcn_rcpf(l3 * l3);
+    const float Rb2 = (l1 * l1) * __builtin_amdgcn_rcpf(fabsf(l2 * l3));
     const float S2 = l1 * l1 + l2 * l2 + l3 * l3;
     return (-expm1f(-Ra2 * inv2a2)) * expf(-Rb2 * inv2b2) * (-expm1f(-S2 * inv2c2));
 }
@@ -264,11 +266,11 @@ __device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const f
         vmax = fmaxf(vmax, sqrtf(gx_ * gx_ + gy_ * gy_ + gz_ * gz_));
         const float gm = fmaxf(fabsf(gx_), fmaxf(fabsf(gy_), fabsf(gz_)));
         if (gm > 0.f) {
-            const float ig = 1.f / gm;
+            const float ig = __builtin_amdgcn_rcpf(gm);
             const float u0 = gx_ * ig, u1 = gy_ * ig, u2 = gz_ * ig;
             const float num = H[0] * u0 * u0 + H[1] * u1 * u1 + H[2] * u2 * u2 +
                               2.f * (H[3] * u0 * u1 + H[4] * u0 * u2 + H[5] * u1 * u2);
-            kap = num / (u0 * u0 + u1 * u1 + u2 * u2);
+            kap = num * __builtin_amdgcn_rcpf(u0 * u0 + u1 * u1 + u2 * u2);  // the sum is >= 1
         }
     }
     float l1, l2, l3;
@@ -278,7 +280,7 @@ __device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const f
         c = 0.5f * __hip_atomic_load(a.fro, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
         if (!(c > 0.f)) c = 1.f;
     }
-    float V = frangi(l1, l2, l3, a.inv2a2, a.inv2b2, 0.5f / (c * c));
+    float V = frangi(l1, l2, l3, a.inv2a2, a.inv2b2, 0.5f * __builtin_amdgcn_rcpf(c * c));
     if constexpr (LAYOUT == DVR_PLANAR) {
         if (!a.first) V = fmaxf(V, ldo<OUT_DT>(a.ves, v));
         else {
