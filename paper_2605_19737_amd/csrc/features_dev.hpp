@@ -32,8 +32,12 @@ __device__ __forceinline__ void eig_trig(T a00, T a11, T a22, T a01, T a02, T a1
     T q = T(0.5) * (c00 * (c11 * c22 - c12 * c12) - c01 * (c01 * c22 - c12 * c02) + c02 * (c01 * c12 - c11 * c02));
     q = q < T(-1) ? T(-1) : (q > T(1) ? T(1) : q);
     const T phi = acos(q) * T(1.0 / 3.0);
-    lmax = m + T(2) * p * cos(phi);
-    lmin = m + T(2) * p * cos(phi + T(2.0943951023931954923));
+    // cos(phi + 2 pi / 3) = -cos(phi) / 2 - sin(phi) sqrt(3) / 2: one sincos instead of two cosines
+    T sp, cp;
+    if constexpr (sizeof(T) == 4) sincosf(phi, &sp, &cp);
+    else sincos(phi, &sp, &cp);
+    lmax = m + T(2) * p * cp;
+    lmin = m - p * (cp + T(1.7320508075688772935) * sp);
     lmid = (a00 + a11 + a22) - lmax - lmin;
 }
 
