@@ -155,3 +155,32 @@ def test_pixel_subset_matches_full():
     sub = oracle.render(w.vol, f, f["gmax"], w.spacing, w.tf_knots, w.tf_rgba, w.params, w.cams, pix=pix)
     for p, (c, i, j) in enumerate(pix):
         np.testing.assert_array_equal(sub["rgba"][p], full["rgba"][c, j, i])
+
+
+def test_ray_split_composites_over():
+    """P12: a ray split at a node plane (segment boundary) gives (C1, T1) for the front slab and
+    (C2, T2) for the back one, and "over", (C1 + T1 C2, T1 T2), reproduces the full ray; the two
+    slabs share the plane's voxels, and the features and gmax are those of the whole volume."""
+    rng = np.random.default_rng(12)
+    dims, sp = (6, 5, 9), (1.0, 1.0, 1.0)
+    vol = rng.uniform(0.05, 0.95, dims[::-1])
+    f = oracle.features(vol, sp, [1.0], c=0.1)
+    knots = np.array([0.0, 0.3, 0.6, 1.0])
+    rgba = np.concatenate([rng.uniform(0, 1, (4, 3)), rng.uniform(0.1, 1.0, (4, 1))], 1)
+    prm = phantoms.render_params(lambda_g=0.6, lambda_k=0.4, kappa0=0.05, lambda_v=1.0, step_vox=0.5)
+    cam = _axis_cam(dims, sp, 2, 1, 4, 3)
+    full = oracle.render(vol, f, f["gmax"], sp, knots, rgba, prm, [cam])["rgba"]
+    m = 4  # split at the node plane z = 4 (8 segments of 0.5 on each side)
+
+    def part(z0, z1, dz):
+        sub = dict(g=f["g"][:, z0:z1], kappa=f["kappa"][z0:z1], V=f["V"][z0:z1])
+        c = phantoms.Camera(0, cam.width, cam.height, (cam.o - np.array([0, 0, dz], np.float32)).astype(np.float32),
+                            cam.d0, cam.du, cam.dv)
+        return oracle.render(vol[z0:z1], sub, f["gmax"], sp, knots, rgba, prm, [c])["rgba"]
+
+    a = part(0, m + 1, 0.0)
+    b = part(m, dims[2], float(m))
+    T1, T2 = 1.0 - a[..., 3], 1.0 - b[..., 3]
+    over = np.concatenate([a[..., :3] + T1[..., None] * b[..., :3], (1.0 - T1 * T2)[..., None]], -1)
+    assert (full[..., 3] > 0.1).all()
+    np.testing.assert_allclose(over, full, rtol=1e-12, atol=1e-15)
