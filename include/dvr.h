@@ -61,8 +61,17 @@ typedef enum dvr_dtype { DVR_F32 = 0, DVR_F16 = 1, DVR_U16 = 2 } dvr_dtype;
  *                     (16 B in F32, 8 B in F16); ves = [nz][ny][nx]; kappa is unused; the intensity
  *                     is the volume, as in PLANAR.  A sample of zero extinction fetches only I; a
  *                     shaded one fetches I, one record and V per corner (the same 24 / 12 bytes per
- *                     voxel as PLANAR, in half the gathers).  Not supported by the batched launch. */
-typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1, DVR_SPLIT = 2 } dvr_layout;
+ *                     voxel as PLANAR, in half the gathers).  Not supported by the batched launch.
+ *   DVR_QUAD:         grad = the SPLIT records, [nz][ny][nx][4] = (gx, gy, gz, kappa); ves =
+ *                     [nz][ny][nx][4] vesselness quads (V(x,y,z), V(x,y+1,z), V(x,y,z+1),
+ *                     V(x,y+1,z+1)), 0 past the last row or slice; iquad = the same quads of the
+ *                     intensity, copied bit for bit from the volume given to dvr_features (whose dtype
+ *                     must be the feature dtype); kappa is unused.  The 8 corners of a cell are the
+ *                     quads of its two x-neighbours, so the raymarcher reads a cell's intensity, and
+ *                     its V, in two loads instead of four (48 / 24 bytes per voxel).  dvr_render and
+ *                     dvr_render_backward read the intensity from iquad and ignore vol.  Not supported
+ *                     by the batched launch. */
+typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1, DVR_SPLIT = 2, DVR_QUAD = 3 } dvr_layout;
 
 typedef struct dvr_grid {
     int32_t nx, ny, nz; /* >= 2 each, nx*ny*nz < 2^31 */
@@ -94,7 +103,7 @@ typedef struct dvr_feature_params {
 typedef struct dvr_features_buf {
     void *grad;   /* device; see dvr_layout */
     void *kappa;  /* device, PLANAR only */
-    void *ves;    /* device, PLANAR only */
+    void *ves;    /* device, PLANAR, SPLIT and QUAD */
     float *gmax;  /* device scalar: max over voxels of |grad I|_2 (the |grad I|_max of Eq. 4) */
     int32_t dtype;  /* DVR_F32 or DVR_F16 (storage type; arithmetic is FP32) */
     int32_t layout; /* dvr_layout */
@@ -105,6 +114,7 @@ typedef struct dvr_features_buf {
                        and skips those bricks (the volume must then be the one the table was built
                        from, and renders sharing one table must be ordered on one stream).
                        dvr_render_backward and the batched launch do not use it. */
+    void *iquad;    /* device, QUAD only: [nz][ny][nx][4] intensity quads, 16-byte aligned; NULL otherwise */
 } dvr_features_buf;
 
 typedef struct dvr_tf {

@@ -70,7 +70,8 @@ def camera_struct(cam):
 class Features:
     """Device-resident feature fields.  planar: grad [3][nz][ny][nx], kappa, ves [nz][ny][nx];
     interleaved: grad [nz][ny][nx][8] = (I, gx, gy, gz, kappa, V, 0, 0); split: grad [nz][ny][nx][4] =
-    (gx, gy, gz, kappa), ves [nz][ny][nx]; gmax: 1-element tensor."""
+    (gx, gy, gz, kappa), ves [nz][ny][nx]; quad: grad as split, ves and iquad [nz][ny][nx][4] quads
+    (v(x,y,z), v(x,y+1,z), v(x,y,z+1), v(x,y+1,z+1)) of V and of the intensity; gmax: 1-element tensor."""
     grad: torch.Tensor
     kappa: torch.Tensor | None
     ves: torch.Tensor | None
@@ -79,6 +80,7 @@ class Features:
     shape: tuple
     spacing: tuple
     bricks: torch.Tensor | None = None  # brick table (flat float32: (min, max) pairs, then mask words), or None
+    iquad: torch.Tensor | None = None  # quad layout: [nz][ny][nx][4] intensity quads
 
     @property
     def dtype(self):
@@ -88,7 +90,8 @@ class Features:
         return abi.FeaturesBuf(self.grad.data_ptr(), self.kappa.data_ptr() if self.kappa is not None else None,
                                self.ves.data_ptr() if self.ves is not None else None, self.gmax.data_ptr(),
                                _dt(self.grad), self.layout,
-                               self.bricks.data_ptr() if self.bricks is not None else None)
+                               self.bricks.data_ptr() if self.bricks is not None else None,
+                               self.iquad.data_ptr() if self.iquad is not None else None)
 
     def brick_minmax(self):
         """[nbz][nby][nbx][2] view of the (min, max) part of the brick table."""
@@ -97,7 +100,8 @@ class Features:
 
     def without_bricks(self):
         """The same fields with no brick table (the raymarch then visits every sample)."""
-        return Features(self.grad, self.kappa, self.ves, self.gmax, self.layout, self.shape, self.spacing, None)
+        return Features(self.grad, self.kappa, self.ves, self.gmax, self.layout, self.shape, self.spacing, None,
+                        self.iquad)
 
 
 def _fparams(sigmas, alpha, beta, c, eig_gap):
@@ -127,13 +131,18 @@ def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANA
         grad = torch.empty((nz, ny, nx, 4), dtype=dtype, device=device)
         kappa = None
         ves = torch.empty((nz, ny, nx), dtype=dtype, device=device)
+    elif layout == abi.DVR_QUAD:
+        grad = torch.empty((nz, ny, nx, 4), dtype=dtype, device=device)
+        kappa = None
+        ves = torch.empty((nz, ny, nx, 4), dtype=dtype, device=device)
     else:
         grad = torch.empty((nz, ny, nx, 8), dtype=dtype, device=device)
         kappa = ves = None
     gmax = torch.empty(1, dtype=torch.float32, device=device)
     nb = math.prod(brick_dims(shape_zyx))
     bt = torch.empty(2 * nb + (nb + 31) // 32, dtype=torch.float32, device=device) if bricks else None
-    return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing), bt)
+    iq = torch.empty((nz, ny, nx, 4), dtype=dtype, device=device) if layout == abi.DVR_QUAD else None
+    return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing), bt, iq)
 
 
 def features_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2):

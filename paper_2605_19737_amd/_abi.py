@@ -16,7 +16,7 @@ DVR_OK = 0
 STATUS = {0: "DVR_OK", -1: "DVR_E_INVALID_ARG", -2: "DVR_E_NULL", -3: "DVR_E_ALIGN", -4: "DVR_E_UNSUPPORTED",
           -5: "DVR_E_NOMEM", -6: "DVR_E_DEVICE", -8: "DVR_E_TIMEOUT", -9: "DVR_E_WORKSPACE"}
 DVR_F32, DVR_F16, DVR_U16 = 0, 1, 2
-DVR_PLANAR, DVR_INTERLEAVED, DVR_SPLIT = 0, 1, 2
+DVR_PLANAR, DVR_INTERLEAVED, DVR_SPLIT, DVR_QUAD = 0, 1, 2, 3
 DVR_MAX_SIGMA = 8
 DVR_BRICK = 4
 DVR_DENOISE_GAUSS, DVR_DENOISE_MEDIAN3 = 0, 1
@@ -34,7 +34,7 @@ class FeatureParams(C.Structure):
 
 class FeaturesBuf(C.Structure):
     _fields_ = [("grad", C.c_void_p), ("kappa", C.c_void_p), ("ves", C.c_void_p), ("gmax", C.c_void_p),
-                ("dtype", C.c_int32), ("layout", C.c_int32), ("bricks", C.c_void_p)]
+                ("dtype", C.c_int32), ("layout", C.c_int32), ("bricks", C.c_void_p), ("iquad", C.c_void_p)]
 
 
 class Peaks(C.Structure):

@@ -86,8 +86,8 @@ dvr_status check_feat_buf(const dvr_features_buf *f, bool need_writable)
     (void)need_writable;
     if (!f) return fail(DVR_E_NULL, "features buffer is NULL");
     if (f->dtype != DVR_F32 && f->dtype != DVR_F16) return fail(DVR_E_UNSUPPORTED, "feature dtype must be F32 or F16");
-    if (f->layout != DVR_PLANAR && f->layout != DVR_INTERLEAVED && f->layout != DVR_SPLIT)
-        return fail(DVR_E_UNSUPPORTED, "feature layout must be PLANAR, INTERLEAVED or SPLIT");
+    if (f->layout != DVR_PLANAR && f->layout != DVR_INTERLEAVED && f->layout != DVR_SPLIT && f->layout != DVR_QUAD)
+        return fail(DVR_E_UNSUPPORTED, "feature layout must be PLANAR, INTERLEAVED, SPLIT or QUAD");
     if (!f->grad || !f->gmax) return fail(DVR_E_NULL, "features grad/gmax is NULL");
     if (!aligned16(f->grad)) return fail(DVR_E_ALIGN, "features grad is not 16-byte aligned");
     if (((uintptr_t)f->gmax & 3u) != 0) return fail(DVR_E_ALIGN, "gmax is not 4-byte aligned");
@@ -95,9 +95,13 @@ dvr_status check_feat_buf(const dvr_features_buf *f, bool need_writable)
         if (!f->kappa || !f->ves) return fail(DVR_E_NULL, "planar features need kappa and ves");
         if (!aligned16(f->kappa) || !aligned16(f->ves)) return fail(DVR_E_ALIGN, "kappa/ves not 16-byte aligned");
     }
-    if (f->layout == DVR_SPLIT) {
-        if (!f->ves) return fail(DVR_E_NULL, "split features need ves");
+    if (f->layout == DVR_SPLIT || f->layout == DVR_QUAD) {
+        if (!f->ves) return fail(DVR_E_NULL, "split and quad features need ves");
         if (!aligned16(f->ves)) return fail(DVR_E_ALIGN, "ves not 16-byte aligned");
+    }
+    if (f->layout == DVR_QUAD) {
+        if (!f->iquad) return fail(DVR_E_NULL, "quad features need iquad");
+        if (!aligned16(f->iquad)) return fail(DVR_E_ALIGN, "iquad not 16-byte aligned");
     }
     if (((uintptr_t)f->bricks & 7u) != 0) return fail(DVR_E_ALIGN, "bricks is not 8-byte aligned");
     return DVR_OK;
@@ -109,7 +113,7 @@ int nbricks(int n) { return (n - 1 + DVR_BRICK - 1) / DVR_BRICK; }
 dvr_status check_feat_size(const dvr_grid *g, const dvr_features_buf *f)
 {
     const uint64_t es = f->dtype == DVR_F32 ? 4u : 2u;
-    const uint64_t per = f->layout == DVR_INTERLEAVED ? 8u * es : (f->layout == DVR_SPLIT ? 4u * es : es);
+    const uint64_t per = f->layout == DVR_INTERLEAVED ? 8u * es : (f->layout == DVR_PLANAR ? es : 4u * es);
     if ((uint64_t)g->nx * (uint64_t)g->ny * (uint64_t)g->nz * per >= ((uint64_t)1 << 32))
         return fail(DVR_E_INVALID_ARG, "feature arrays of this grid exceed 4 GiB (32-bit offsets)");
     return DVR_OK;
@@ -300,6 +304,13 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
     if (ws_bytes < features_ws_bytes(grid))
         return fail(DVR_E_WORKSPACE, "workspace of %zu bytes is smaller than the required %zu", ws_bytes,
                     features_ws_bytes(grid));
+    // QUAD runs the SPLIT pass with V written plainly into the iquad array, then builds both quads
+    dvr_features_buf run = *out;
+    if (out->layout == DVR_QUAD) {
+        if (vol_dtype != out->dtype) return fail(DVR_E_UNSUPPORTED, "QUAD features need the volume in the feature dtype");
+        run.layout = DVR_SPLIT;
+        run.ves = out->iquad;
+    }
     float *scalars = (float *)ws;
     float *fields = (float *)((char *)ws + 256);
     hipError_t e = dvr::launch_init_scalars(out->gmax, scalars, stream);
@@ -311,7 +322,7 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
             const double sg = fp->sigma_mm[sc];
             for (int a = 0; a < 3; ++a) axis_taps(sg / h[a], h[a], taps.ax[a]);
             taps.sigma2 = (float)(sg * sg);
-            e = dvr::launch_features_scale(vol, vol_dtype, *grid, taps, sc, sc == fp->nsigma - 1, *fp, *out, fields,
+            e = dvr::launch_features_scale(vol, vol_dtype, *grid, taps, sc, sc == fp->nsigma - 1, *fp, run, fields,
                                            scalars, pass == 0, stream);
             if (e != hipSuccess) return dev_fail(e, "features launch");
         }
@@ -319,6 +330,12 @@ dvr_status dvr_features(const void *vol, int32_t vol_dtype, const dvr_grid *grid
     if (out->bricks) {
         e = dvr::launch_bricks(vol, vol_dtype, *grid, *out, stream);
         if (e != hipSuccess) return dev_fail(e, "brick table launch");
+    }
+    if (out->layout == DVR_QUAD) {
+        // V quads from the plain V first, then the intensity quads over it
+        e = dvr::launch_quads(out->iquad, out->ves, *grid, out->dtype, stream);
+        if (e == hipSuccess) e = dvr::launch_quads(vol, out->iquad, *grid, out->dtype, stream);
+        if (e != hipSuccess) return dev_fail(e, "quad launch");
     }
     return DVR_OK;
 }
@@ -390,7 +407,7 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
     if (s) return s;
     if ((s = check_feat_buf(feat, false))) return s;
     if ((s = check_feat_size(grid, feat))) return s;
-    if (feat->layout != DVR_INTERLEAVED) {
+    if (feat->layout != DVR_INTERLEAVED && feat->layout != DVR_QUAD) {
         if (!vol) return fail(DVR_E_NULL, "vol is NULL (planar and split features sample it)");
         if (!aligned16(vol)) return fail(DVR_E_ALIGN, "vol is not 16-byte aligned");
         if (vol_dtype != feat->dtype) return fail(DVR_E_UNSUPPORTED, "planar render needs vol dtype == feature dtype");
@@ -427,7 +444,7 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
         }
     }
     memset(&a, 0, sizeof a);
-    a.feat.vol = vol;
+    a.feat.vol = feat->layout == DVR_QUAD ? feat->iquad : vol;
     a.feat.grad = feat->grad;
     a.feat.kappa = feat->kappa;
     a.feat.ves = feat->ves;

@@ -119,6 +119,9 @@ size_t features_bwd_ws_bytes(const dvr_grid &g, const FeatBwdPlan &p);
 hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid &g, const FeatBwdPlan &p,
                                     const float *dfeat, const float *dgmax, float *dvol, void *ws, hipStream_t st);
 hipError_t launch_bricks(const void *vol, int vol_dt, const dvr_grid &g, const dvr_features_buf &out, hipStream_t st);
+// dst[v] = (src(x,y,z), src(x,y+1,z), src(x,y,z+1), src(x,y+1,z+1)) with 0 past the last row or slice
+// (bit copies of dtype elements): the quads of the QUAD feature layout
+hipError_t launch_quads(const void *src, void *dst, const dvr_grid &g, int dtype, hipStream_t st);
 
 hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, int64_t n, uint32_t *ws,
                             hipStream_t st);

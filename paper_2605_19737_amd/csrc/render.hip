@@ -191,6 +191,8 @@ static hipError_t launch_any(const RenderArgs &a, hipStream_t st, bool bwd)
         else if (lay == DVR_INTERLEAVED && dt == DVR_F16) e = launch_k<DVR_INTERLEAVED, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
         else if (lay == DVR_SPLIT && dt == DVR_F32) e = launch_k<DVR_SPLIT, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
         else if (lay == DVR_SPLIT && dt == DVR_F16) e = launch_k<DVR_SPLIT, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
+        else if (lay == DVR_QUAD && dt == DVR_F32) e = launch_k<DVR_QUAD, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
+        else if (lay == DVR_QUAD && dt == DVR_F16) e = launch_k<DVR_QUAD, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
         else e = hipErrorInvalidValue;
         if (e != hipSuccess) return e;
     }

@@ -171,11 +171,12 @@ __device__ __forceinline__ bool brick_empty(const TFShared<KMAX> &sh, const floa
 }
 
 // ------------------------------------------------------------------------------------------------
-// Feature fetch.  LAYOUT/DT select planar planes, interleaved records, or the split layout (I and V
-// planes plus a (gx, gy, gz, k) record, addressed at 4x the plane offsets).
+// Feature fetch.  LAYOUT/DT select planar planes, interleaved records, the split layout (I and V
+// planes plus a (gx, gy, gz, k) record, addressed at 4x the plane offsets), or the quad layout (the
+// split records, and I and V as per-voxel (y, z) quads, also addressed at 4x the plane offsets).
 template <int LAYOUT, int DT>
 struct Vox {
-    Buf b[6];  // planar: I, gx, gy, gz, kappa, V;  interleaved: b[0] = records;  split: I, records, V
+    Buf b[6];  // planar: I, gx, gy, gz, kappa, V;  interleaved: b[0] = records;  split, quad: I, records, V
     uint32_t sx, sy, sz;  // byte strides of +1 in x, y, z (split: in the planes)
 
     __device__ __forceinline__ void init(const KFeat &f, const KGrid &g)
@@ -191,11 +192,12 @@ struct Vox {
             b[3] = make_buf(gp + (size_t)2 * N * es, N * es);
             b[4] = make_buf(f.kappa, N * es);
             b[5] = make_buf(f.ves, N * es);
-        } else if constexpr (LAYOUT == DVR_SPLIT) {
+        } else if constexpr (LAYOUT == DVR_SPLIT || LAYOUT == DVR_QUAD) {
             es = ElemSize<DT>::v;
-            b[0] = make_buf(f.vol, N * es);
+            const uint32_t q = (LAYOUT == DVR_QUAD) ? 4u : 1u;
+            b[0] = make_buf(f.vol, N * q * es);
             b[1] = make_buf(f.grad, N * 4u * es);
-            b[2] = make_buf(f.ves, N * es);
+            b[2] = make_buf(f.ves, N * q * es);
         } else {
             es = (DT == DVR_F32) ? 32u : 16u;
             b[0] = make_buf(f.grad, N * es);
@@ -255,10 +257,33 @@ struct CornerCache {
         feat = false;
     }
 
+    // quad layout: the quads of voxels x and x + 1 (byte offset off and the next quad) are the
+    // corners (y, z), (y+1, z), (y, z+1), (y+1, z+1) of the cell's two x-columns, channel CH
+    template <int CH>
+    __device__ __forceinline__ void quad_pair(const Buf &b, uint32_t off)
+    {
+        if constexpr (DT == DVR_F32) {
+            const f32x4 a = __builtin_bit_cast(f32x4, ld4(b, off));
+            const f32x4 d = __builtin_bit_cast(f32x4, ld4(b, off + 16u));
+            v[0][CH] = a.x; v[2][CH] = a.y; v[4][CH] = a.z; v[6][CH] = a.w;
+            v[1][CH] = d.x; v[3][CH] = d.y; v[5][CH] = d.z; v[7][CH] = d.w;
+        } else {
+            const f16x4 a = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0));
+            const f16x4 d = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(b.r, off + 8u, 0, 0));
+            v[0][CH] = (float)a.x; v[2][CH] = (float)a.y; v[4][CH] = (float)a.z; v[6][CH] = (float)a.w;
+            v[1][CH] = (float)d.x; v[3][CH] = (float)d.y; v[5][CH] = (float)d.z; v[7][CH] = (float)d.w;
+        }
+    }
+
     __device__ __forceinline__ void need_I(const Vox<LAYOUT, DT> &vx, const Corners &c)
     {
         if (c.off[0] == base) return;
         base = c.off[0];
+        if constexpr (LAYOUT == DVR_QUAD) {
+            quad_pair<0>(vx.b[0], c.off[0] << 2);
+            feat = false;
+            return;
+        }
         if constexpr (LAYOUT != DVR_INTERLEAVED && DT == DVR_F32) {
             // corners x and x + 1 are adjacent floats: one 8-byte load per (y, z) row of the cell
 #pragma unroll
@@ -322,9 +347,10 @@ struct CornerCache {
                     else v[e][ch] = ldh(vx.b[ch], off);
                 }
             }
-        } else if constexpr (LAYOUT == DVR_SPLIT) {
+        } else if constexpr (LAYOUT == DVR_SPLIT || LAYOUT == DVR_QUAD) {
             if (feat) return;
             feat = true;
+            if constexpr (LAYOUT == DVR_QUAD) quad_pair<5>(vx.b[2], c.off[0] << 2);
 #pragma unroll
             for (int e = 0; e < 8; ++e) {
                 const uint32_t off = c.off[e >> 1] + ((e & 1) ? vx.sx : 0u);
@@ -334,7 +360,7 @@ struct CornerCache {
                     v[e][2] = r.y;
                     v[e][3] = r.z;
                     v[e][4] = r.w;
-                    if ((e & 1) == 0) {  // V of corners x and x + 1 in one 8-byte load
+                    if (LAYOUT == DVR_SPLIT && (e & 1) == 0) {  // V of corners x and x + 1 in one 8-byte load
                         const f32x2 p = ld2f(vx.b[2], off);
                         v[e][5] = p.x;
                         v[e + 1][5] = p.y;
@@ -345,7 +371,7 @@ struct CornerCache {
                     v[e][2] = (float)r.y;
                     v[e][3] = (float)r.z;
                     v[e][4] = (float)r.w;
-                    v[e][5] = ldh(vx.b[2], off);
+                    if constexpr (LAYOUT == DVR_SPLIT) v[e][5] = ldh(vx.b[2], off);
                 }
             }
         }

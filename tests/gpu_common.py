@@ -40,11 +40,13 @@ def feats_np(f: dvr.Features):
         k = f.kappa.float().cpu().numpy().astype(np.float64)
         V = f.ves.float().cpu().numpy().astype(np.float64)
         I = None
-    elif f.layout == abi.DVR_SPLIT:
+    elif f.layout in (abi.DVR_SPLIT, abi.DVR_QUAD):
         rec = f.grad.float().cpu().numpy().astype(np.float64)
         g = np.moveaxis(rec[..., 0:3], -1, 0)
         k = rec[..., 3]
         V = f.ves.float().cpu().numpy().astype(np.float64)
+        if f.layout == abi.DVR_QUAD:
+            V = V[..., 0]
         I = None
     else:
         rec = f.grad.float().cpu().numpy().astype(np.float64)

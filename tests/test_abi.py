@@ -253,3 +253,24 @@ def test_feature_adjoint_validation(L):
                    C.byref(tf), C.byref(_rp()), arr, 1, C.byref(st), C.c_void_p(FAKE), C.c_void_p(FAKE), None,
                    C.byref(abi.FeatureGrads(FAKE + 2, FAKE)), None)
     assert s == -3
+
+
+def test_quad_layout_validation(L):
+    """The quad layout needs an aligned iquad array and the volume in the feature dtype; an unknown
+    layout is rejected."""
+    g, fp = _grid(), _fp()
+
+    def call(fb, vol_dt=abi.DVR_F32):
+        return _status(L, "dvr_features", C.c_void_p(FAKE), vol_dt, C.byref(g), C.byref(fp), C.byref(fb),
+                       C.c_void_p(FAKE), 1 << 30, None)
+
+    s, msg = call(abi.FeaturesBuf(FAKE, None, FAKE, FAKE, abi.DVR_F32, abi.DVR_QUAD, None, None))
+    assert s == -2 and "iquad" in msg
+    s, msg = call(abi.FeaturesBuf(FAKE, None, FAKE, FAKE, abi.DVR_F32, abi.DVR_QUAD, None, FAKE + 4))
+    assert s == -3 and "iquad" in msg
+    s, msg = call(abi.FeaturesBuf(FAKE, None, None, FAKE, abi.DVR_F32, abi.DVR_QUAD, None, FAKE))
+    assert s == -2 and "ves" in msg
+    s, msg = call(abi.FeaturesBuf(FAKE, None, FAKE, FAKE, abi.DVR_F16, abi.DVR_QUAD, None, FAKE))
+    assert s == -4 and "QUAD" in msg
+    s, msg = call(abi.FeaturesBuf(FAKE, None, FAKE, FAKE, abi.DVR_F32, 4, None, FAKE))
+    assert s == -4 and "layout" in msg
