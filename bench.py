@@ -105,13 +105,14 @@ def main():
     cams = [dvr.camera_struct(c) for c in w.cams]
     nvox = vol.numel()
     nz, ny, nx = vol.shape
-    # FP32 features in the split layout (I and V planes, one (gx, gy, gz, k) record per voxel): the
-    # same values as planar, half the gathers per shaded corner.  No brick table here: the head's
+    # FP32 features in the quad layout (one (gx, gy, gz, k) record per voxel; V and the intensity as
+    # per-voxel (y, z) quads): the same values as planar, a cell's corners in 2 + 8 + 2 loads instead
+    # of 8 + 8 + 8.  No brick table here: the head's
     # Rician background leaves few empty 4^3 bricks, and the per-brick lookups cost more than the
     # transparent samples they save (the table pays off where empty space is clean: see the
     # 512x512x400 leg)
     from paper_2605_19737_amd import _abi as abi_
-    feats = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float32, abi_.DVR_SPLIT, bricks=False)
+    feats = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float32, abi_.DVR_QUAD, bricks=False)
     wsb = dvr.features_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c)
     ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
     V = len(cams)
@@ -124,7 +125,7 @@ def main():
         e0.record(stream)
         dvr.features(vol, w.spacing, w.sigmas, c=w.c, layout=feats.layout, out=feats, ws=ws)
         e1.record(stream)
-        _, T, k = dvr.render(vol, feats, knots, tf, w.params, cams, out=img, counters=counters)
+        _, T, k = dvr.render(vol, feats, knots, tf, w.params, cams, out=img)
         e2.record(stream)
         if timing is not None:
             timing.append((e0, e1, e2))
@@ -145,6 +146,9 @@ def main():
     t_feat = sum(a.elapsed_time(b) for a, b, _ in timing) / 1e3
     t_rend = sum(b.elapsed_time(c) for _, b, c in timing) / 1e3
     t_step = sum(a.elapsed_time(c) for a, _, c in timing) / 1e3
+    # sample counts from one instrumented render after the timed steps (the counts are deterministic;
+    # the counters' same-address atomics would otherwise add ~0.15 ms per view to the timed raymarch)
+    dvr.render(vol, feats, knots, tf, w.params, cams, out=img, counters=counters)
     evaluated, shaded = (int(x) for x in counters.cpu().tolist())
     log(f"step {1e3 * t_step / args.steps:.2f} ms (features {1e3 * t_feat / args.steps:.3f} ms, render "
         f"{1e3 * t_rend / args.steps:.2f} ms); samples/step evaluated {evaluated:.4g} shaded {shaded:.4g}; wall {wall:.2f}s")
@@ -167,7 +171,7 @@ def main():
                    "views_per_launch": tr.get("views_per_launch"), "source_sha": sha}
     roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
                 "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
-                "traffic": traffic, "kernel": "k_render (FP32 split layout, K<=8)",
+                "traffic": traffic, "kernel": "k_render (FP32 quad layout, K<=8)",
                 "avg_launch_ms": round(1e3 * render_launch_s, 4),
                 "flops_per_launch": flops_per_step / launches_per_step,
                 "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4)}
@@ -301,18 +305,18 @@ def leg_feature_adjoint(w, vol, feats, knots, tf, cams, stream, dvr, torch, np, 
     out = {"render_bwd_ms_per_view": plain / len(sel), "render_bwd_feature_grads_ms_per_view": fgt / len(sel),
            "features_backward_ms": fb, "features_backward_voxels_per_s": N / (fb * 1e-3),
            "features_backward_hbm_frac": 32.0 * N / (fb * 1e-3) / 8e12, "workspace_bytes": nfb,
-           "workload": f"head {tuple(vol.shape)} FP32 split layout, sigma {{1,2,3}} mm, {len(sel)} views 1024^2"}
+           "workload": f"head {tuple(vol.shape)} FP32 quad layout, sigma {{1,2,3}} mm, {len(sel)} views 1024^2"}
     log(f"render adjoint {out['render_bwd_ms_per_view']:.3f} ms/view, with feature gradients "
         f"{out['render_bwd_feature_grads_ms_per_view']:.3f} ms/view; feature-pass adjoint {fb:.2f} ms")
     return out
 
 
 def leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log):
-    """Same head workload with FP16 volume and FP16 interleaved feature records (FP32 arithmetic)."""
+    """Same head workload with FP16 volume and FP16 quad-layout features (FP32 arithmetic)."""
     from paper_2605_19737_amd import _abi as abi
-    log("FP16-record leg: same step with an FP16 volume and FP16 feature records")
+    log("FP16 leg: same step with an FP16 volume and FP16 quad-layout features")
     v16 = vol.half()
-    f16 = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float16, abi.DVR_INTERLEAVED)
+    f16 = dvr.alloc_features(tuple(vol.shape), w.spacing, torch.float16, abi.DVR_QUAD, bricks=False)
     ws = torch.empty(dvr.features_workspace_bytes(tuple(vol.shape), w.spacing, w.sigmas, c=w.c), dtype=torch.uint8,
                      device=vol.device)
     img = torch.empty((len(cams), 1024, 1024, 4), dtype=torch.float32, device=vol.device)
@@ -321,21 +325,22 @@ def leg_fp16(w, vol, knots, tf, cams, stream, K, dvr, torch, log):
     for it in range(K + 1):
         a, b, c = (torch.cuda.Event(enable_timing=True) for _ in range(3))
         a.record(stream)
-        dvr.features(v16, w.spacing, w.sigmas, c=w.c, dtype=torch.float16, layout=abi.DVR_INTERLEAVED, out=f16, ws=ws)
+        dvr.features(v16, w.spacing, w.sigmas, c=w.c, dtype=torch.float16, layout=abi.DVR_QUAD, out=f16, ws=ws)
         b.record(stream)
-        dvr.render(None, f16, knots, tf, w.params, cams, out=img, counters=cnt)
+        dvr.render(None, f16, knots, tf, w.params, cams, out=img)
         c.record(stream)
         if it > 0:
             ev.append((a, b, c))
     torch.cuda.synchronize()
     tf_ = sum(a.elapsed_time(b) for a, b, _ in ev) / 1e3
     tr = sum(b.elapsed_time(c) for _, b, c in ev) / 1e3
+    dvr.render(None, f16, knots, tf, w.params, cams, out=img, counters=cnt)  # counts, untimed
     evaluated = int(cnt[0].item())
     out = {"samples_per_s": evaluated * K / (tf_ + tr), "render_samples_per_s": evaluated * K / tr,
            "render_ms_per_view": 1e3 * tr / (K * len(cams)), "features_ms": 1e3 * tf_ / K,
            "image_error_bound": "compute 1e-5 of range given the stored FP16 values; storage 2^-11 per feature; "
                                 "end to end 5.4e-4 max / 1.2e-5 mean measured at 512x512x400"}
-    log(f"FP16 records: {out['samples_per_s']:.4g} samples/s over the step ({out['render_ms_per_view']:.3f} ms/view)")
+    log(f"FP16 quad features: {out['samples_per_s']:.4g} samples/s over the step ({out['render_ms_per_view']:.3f} ms/view)")
     return out
 
 
@@ -427,7 +432,7 @@ def leg_c5(dev, stream, dvr, torch, np, log):
         dvr.features(v16, w.spacing, w.sigmas, c=w.c, eig_gap=1e-3, dtype=torch.float16, layout=abi.DVR_INTERLEAVED,
                      out=f, ws=wsf)
         ev[2].record(stream)
-        img, T, k = dvr.render(None, f, knots, tf, w.params, cams, counters=cnt)
+        img, T, k = dvr.render(None, f, knots, tf, w.params, cams)
         ev[3].record(stream)
         if it == 0:
             target, _, _ = dvr.render(None, f, knots, tgt, w.params, cams, want_state=False)
@@ -437,6 +442,7 @@ def leg_c5(dev, stream, dvr, torch, np, log):
         if it > 0:
             times.append([ev[i].elapsed_time(ev[i + 1]) for i in range(4)])
     t = np.median(np.array(times), axis=0)
+    dvr.render(None, f, knots, tf, w.params, cams, counters=cnt)  # sample counts, untimed
     evaluated = int(cnt[0].item())
     # automatic tissue windows on the normalized volume: histogram (2 B/voxel read), peaks, TF
     ht = []

@@ -98,7 +98,7 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
         if (L.T_last) L.T_last[pix] = o.Tprev;
         if (L.k_last) L.k_last[pix] = o.last;
     }
-    if (L.counters) count_samples(L.counters, o.last, o.shaded);
+    if (L.counters) count_samples<4>(L.counters, o.last, o.shaded);
 }
 
 template <int LAYOUT, int DT, int KMAX, bool FG>

@@ -549,17 +549,33 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
     return o_;
 }
 
-// wave-level sum of two per-lane counts, one 64-bit atomic each per wave (every lane must be here)
+// Workgroup sum of two per-lane counts (NW waves), one 64-bit atomic each per workgroup: the adds all
+// go to the same two words, which the L2 serializes, so one per wave would cost a third of the
+// raymarch.  Every thread of the workgroup must be here.
+template <int NW>
 __device__ __forceinline__ void count_samples(unsigned long long *counters, int last, int shaded)
 {
+    __shared__ uint32_t part[NW][2];
     uint32_t ev = (uint32_t)(last + 1), ns = (uint32_t)shaded;
     for (int o = 32; o > 0; o >>= 1) {
         ev += __shfl_xor(ev, o, 64);
         ns += __shfl_xor(ns, o, 64);
     }
+    const uint32_t wv = threadIdx.x >> 6;
     if ((threadIdx.x & 63u) == 0) {
-        atomicAdd(counters, (unsigned long long)ev);
-        atomicAdd(counters + 1, (unsigned long long)ns);
+        part[wv][0] = ev;
+        part[wv][1] = ns;
+    }
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned long long e = 0, n = 0;
+#pragma unroll
+        for (int w = 0; w < NW; ++w) {
+            e += part[w][0];
+            n += part[w][1];
+        }
+        atomicAdd(counters, e);
+        atomicAdd(counters + 1, n);
     }
 }
 
