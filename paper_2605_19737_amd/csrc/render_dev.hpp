@@ -258,7 +258,8 @@ struct CornerCache {
     }
 
     // quad layout: the quads of voxels x and x + 1 (byte offset off and the next quad) are the
-    // corners (y, z), (y+1, z), (y, z+1), (y+1, z+1) of the cell's two x-columns, channel CH
+    // corners (y, z), (y+1, z), (y, z+1), (y+1, z+1) of the cell's two x-columns, channel CH; the two
+    // 8-byte F16 quads are adjacent, so they come in one 16-byte load
     template <int CH>
     __device__ __forceinline__ void quad_pair(const Buf &b, uint32_t off)
     {
@@ -268,10 +269,9 @@ struct CornerCache {
             v[0][CH] = a.x; v[2][CH] = a.y; v[4][CH] = a.z; v[6][CH] = a.w;
             v[1][CH] = d.x; v[3][CH] = d.y; v[5][CH] = d.z; v[7][CH] = d.w;
         } else {
-            const f16x4 a = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(b.r, off, 0, 0));
-            const f16x4 d = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(b.r, off + 8u, 0, 0));
-            v[0][CH] = (float)a.x; v[2][CH] = (float)a.y; v[4][CH] = (float)a.z; v[6][CH] = (float)a.w;
-            v[1][CH] = (float)d.x; v[3][CH] = (float)d.y; v[5][CH] = (float)d.z; v[7][CH] = (float)d.w;
+            const f16x8 a = __builtin_bit_cast(f16x8, ld4(b, off));
+            v[0][CH] = (float)a[0]; v[2][CH] = (float)a[1]; v[4][CH] = (float)a[2]; v[6][CH] = (float)a[3];
+            v[1][CH] = (float)a[4]; v[3][CH] = (float)a[5]; v[5][CH] = (float)a[6]; v[7][CH] = (float)a[7];
         }
     }
 
@@ -366,11 +366,18 @@ struct CornerCache {
                         v[e + 1][5] = p.y;
                     }
                 } else {
-                    const f16x4 r = __builtin_bit_cast(f16x4, __builtin_amdgcn_raw_buffer_load_b64(vx.b[1].r, off << 2, 0, 0));
-                    v[e][1] = (float)r.x;
-                    v[e][2] = (float)r.y;
-                    v[e][3] = (float)r.z;
-                    v[e][4] = (float)r.w;
+                    // the 8-byte records of corners x and x + 1 are adjacent: one 16-byte load
+                    if ((e & 1) == 0) {
+                        const f16x8 r = __builtin_bit_cast(f16x8, ld4(vx.b[1], off << 2));
+                        v[e][1] = (float)r[0];
+                        v[e][2] = (float)r[1];
+                        v[e][3] = (float)r[2];
+                        v[e][4] = (float)r[3];
+                        v[e + 1][1] = (float)r[4];
+                        v[e + 1][2] = (float)r[5];
+                        v[e + 1][3] = (float)r[6];
+                        v[e + 1][4] = (float)r[7];
+                    }
                     if constexpr (LAYOUT == DVR_SPLIT) v[e][5] = ldh(vx.b[2], off);
                 }
             }
