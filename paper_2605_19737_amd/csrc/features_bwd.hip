@@ -307,6 +307,64 @@ __global__ __launch_bounds__(256) void k_tx(const float *__restrict__ Hb, float 
     for (int k = 0; k < 6; ++k) X[(size_t)k * N + row + x] = acc[k];
 }
 
+// The same x transpose for one chunk of up to 256 outputs of one row per workgroup (blockIdx.x =
+// y + ny z, blockIdx.y = chunk): the six fields of the chunk and its R-voxel halo are staged in LDS
+// once, instead of 6 (2R + 1) global loads per output.  An output whose contributing forward rows
+// i in [x - R, x + R] all lie in [R, nx - 1 - R] (no clamped or one-sided taps) takes the weights from
+// the taps themselves, which is what the band table holds there (a single tap per entry); the
+// others read the band table.  Same products in the same order as k_tx: the same bits.
+constexpr int kTxChunk = 256;
+__global__ __launch_bounds__(256) void k_tx_lds(const float *__restrict__ Hb, float *__restrict__ X,
+                                                const float *__restrict__ B, AxisTaps t, int nx, int ny, int nz)
+{
+    __shared__ float s[6][kTxChunk + 2 * (DVR_MAX_RADIUS + 1)];
+    __shared__ float tg[DVR_MAX_RADIUS + 2], td1[DVR_MAX_RADIUS + 2], td2[DVR_MAX_RADIUS + 2];
+    const int R = t.R, W = 2 * R + 1;
+    const size_t N = (size_t)nx * (size_t)ny * (size_t)nz;
+    const size_t rbase = (size_t)blockIdx.x * (size_t)nx;
+    const int x0 = (int)blockIdx.y * kTxChunk;
+    const int lo = max(0, x0 - R), hi = min(nx, x0 + kTxChunk + R);
+    for (int p = (int)threadIdx.x; p < hi - lo; p += 256) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s[f][p] = Hb[(size_t)f * N + rbase + (size_t)(lo + p)];
+    }
+    if (threadIdx.x <= (unsigned)R) {
+        tg[threadIdx.x] = t.G[threadIdx.x];
+        td1[threadIdx.x] = t.D1[threadIdx.x];
+        td2[threadIdx.x] = t.D2[threadIdx.x];
+    }
+    __syncthreads();
+    const int x = x0 + (int)threadIdx.x;
+    if (x >= nx) return;
+    const bool interior = x - 2 * R >= 0 && x + 2 * R <= nx - 1;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    const int i0 = max(0, x - R), i1 = min(nx - 1, x + R);
+    for (int i = i0; i <= i1; ++i) {
+        const int d = x - i + R;
+        float b0, b1, b2;
+        if (interior) {
+            const int m = x - i, am = m < 0 ? -m : m;
+            b0 = tg[am];
+            b1 = m > 0 ? td1[am] : (m < 0 ? -td1[am] : 0.f);
+            b2 = td2[am];
+        } else {
+            b0 = B[(size_t)d * nx + i];
+            b1 = B[(size_t)(W + d) * nx + i];
+            b2 = B[(size_t)(2 * W + d) * nx + i];
+        }
+        const int li = i - lo;
+        acc[0] = fmaf(b2, s[0][li], acc[0]);
+        acc[1] = fmaf(b0, s[1][li], acc[1]);
+        acc[2] = fmaf(b0, s[2][li], acc[2]);
+        acc[3] = fmaf(b1, s[3][li], acc[3]);
+        acc[4] = fmaf(b1, s[4][li], acc[4]);
+        acc[5] = fmaf(b0, s[5][li], acc[5]);
+    }
+    const size_t o = rbase + (size_t)x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[(size_t)k * N + o] = acc[k];
+}
+
 // y: the three z-groups: Y0 = G^T X_xx + (D2 G)^T X_yy + (D1 G)^T X_xy (z operator G),
 // Y1 = G^T X_xz + (D1 G)^T X_yz (z operator D1 G), Y2 = G^T X_zz (z operator D2 G)
 __global__ __launch_bounds__(256) void k_ty(const float *__restrict__ X, float *__restrict__ Y,
@@ -529,7 +587,12 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
                                s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
                                p.inv2h[2]);
         float *X = Hs, *Y = w.zws;  // this scale's H is no longer needed
-        hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
+        const unsigned xchunks = (unsigned)((g.nx + kTxChunk - 1) / kTxChunk);
+        if (xchunks <= 65535u)
+            hipLaunchKernelGGL(k_tx_lds, dim3((unsigned)g.ny * (unsigned)g.nz, xchunks), dim3(256), 0, st, w.Hb, X,
+                               bt[s][0], p.taps[s].ax[0], g.nx, g.ny, g.nz);
+        else
+            hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
         hipLaunchKernelGGL(k_ty, pgrid, dim3(256), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
         hipLaunchKernelGGL(k_tz, pgrid, dim3(256), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
         if ((e = hipGetLastError()) != hipSuccess) return e;
