@@ -77,6 +77,8 @@ def main():
     ap.add_argument("--no-c5-leg", action="store_true")
     ap.add_argument("--no-feature-adjoint-leg", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="just the timed head-phantom steps (for profiling)")
+    ap.add_argument("--only-adjoint", action="store_true",
+                    help="just one render adjoint of 8 head views (every 45th) after one forward (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -119,6 +121,17 @@ def main():
     img = torch.empty((V, 1024, 1024, 4), dtype=torch.float32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.only_adjoint:
+        dvr.features(vol, w.spacing, w.sigmas, c=w.c, layout=feats.layout, out=feats, ws=ws)
+        sel = cams[::45][:8]
+        im8, T8, k8 = dvr.render(vol, feats, knots, tf, w.params, sel)
+        g = torch.Generator(device=dev).manual_seed(45)
+        dout = 0.01 * torch.randn(im8.shape, generator=g, device=dev)
+        dvr.render_backward(vol, feats, knots, tf, w.params, sel, T8, k8, dout)
+        torch.cuda.synchronize()
+        log("adjoint of 8 head views done")
+        return
 
     def step(timing=None):
         e0, e1, e2 = (torch.cuda.Event(enable_timing=True) for _ in range(3))
