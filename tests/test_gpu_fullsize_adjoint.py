@@ -1,5 +1,5 @@
 """Full-size parity of the gradients on the benchmarked workload (181x217x181 head, 3 scales, FP32
-split layout, perspective views at 1024^2), through the C ABI:
+quad layout, perspective views at 1024^2), through the C ABI:
   * dvr_render_backward_features on four whole 1024^2 views: dL/dTF, dL/dI through the TF lookup
     (corners of samples within 1e-6 of a TF knot left out, counted) and dL/d(g, k, V, gmax) against
     the oracle render's reverse mode fed the GPU's own feature values (normwise <= 1e-4);
@@ -31,9 +31,9 @@ def _nerr(x, r):
 
 def test_head_full_size_gradients():
     w = phantoms.c2(1024, 1024, views=[0, 90, 200, 300])
-    print("[full-size adjoint] head 181x217x181, sigma {1,2,3}, 4 views 1024^2, split FP32", flush=True)
+    print("[full-size adjoint] head 181x217x181, sigma {1,2,3}, 4 views 1024^2, quad FP32", flush=True)
     dv = to_dev(w.vol)
-    f = dvr.features(dv, w.spacing, w.sigmas, c=w.c, layout=abi.DVR_SPLIT)
+    f = dvr.features(dv, w.spacing, w.sigmas, c=w.c, layout=abi.DVR_QUAD)
     kn, rg = tf_dev(w)
     img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
     rng = np.random.default_rng(21)

@@ -77,11 +77,15 @@ def test_render_c1():
     assert float(img[..., 3].max()) > 0.3
 
 
-def test_render_head_full_size_sampled():
+@pytest.mark.parametrize("layout", [abi.DVR_QUAD, abi.DVR_PLANAR])
+def test_render_head_full_size_sampled(layout):
     """The benchmarked launch: 1024^2 perspective views of the head phantom with 3-scale features,
-    8-knot TF, early termination 0.99, rendered in one call; compared on 6000 sampled pixels."""
+    8-knot TF, early termination 0.99, rendered in one call; compared on 6000 sampled pixels.  The
+    quad layout without a brick table is what the benchmark times."""
     w = phantoms.c2(1024, 1024, views=[0, 37, 90, 200])
-    dv, f = _gpu_scene(w)
+    dv, f = _gpu_scene(w, layout=layout)
+    if layout == abi.DVR_QUAD:
+        f = f.without_bricks()
     kn, rg = tf_dev(w)
     img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
     of = _oracle_feats(dv, w)
