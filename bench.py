@@ -78,7 +78,8 @@ def main():
     ap.add_argument("--no-feature-adjoint-leg", action="store_true")
     ap.add_argument("--only-main", action="store_true", help="just the timed head-phantom steps (for profiling)")
     ap.add_argument("--only-adjoint", action="store_true",
-                    help="just one render adjoint of 8 head views (every 45th) after one forward (for profiling)")
+                    help="just the render adjoint of 8 head views (every 45th) after one forward, without and then "
+                         "with the feature gradients (for profiling)")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -129,8 +130,9 @@ def main():
         g = torch.Generator(device=dev).manual_seed(45)
         dout = 0.01 * torch.randn(im8.shape, generator=g, device=dev)
         dvr.render_backward(vol, feats, knots, tf, w.params, sel, T8, k8, dout)
+        dvr.render_backward(vol, feats, knots, tf, w.params, sel, T8, k8, dout, want_features=True)
         torch.cuda.synchronize()
-        log("adjoint of 8 head views done")
+        log("adjoint of 8 head views done (without, then with the feature gradients)")
         return
 
     def step(timing=None):
