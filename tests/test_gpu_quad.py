@@ -118,3 +118,33 @@ def test_quad_needs_matching_volume_dtype():
     v = to_dev(w.vol)
     with pytest.raises(abi.DVRError):
         dvr.features(v, w.spacing, w.sigmas, c=w.c, dtype=torch.float16, layout=abi.DVR_QUAD)
+
+
+@pytest.mark.parametrize("dims", [(2, 3, 5), (2, 2, 2), (7, 2, 3)])
+def test_quad_render_tiny_grids(dims):
+    """Grids where every cell touches a last row or slice (the quads' zero padding sits under the
+    weight-0 corners of samples on the faces): the same bits as the split layout, and the oracle."""
+    sp = (1.0, 0.9, 1.2)
+    vol = phantoms.small_random(11, dims, sp, lo=0.05, hi=0.95)
+    v = to_dev(vol)
+    knots = np.float32([0.0, 0.3, 0.6, 1.0]).astype(np.float64)
+    rgba = np.float32([[0.2, 0.4, 0.6, 0.5], [0.9, 0.3, 0.1, 1.2], [0.1, 0.8, 0.3, 0.8],
+                       [0.7, 0.7, 0.9, 1.5]]).astype(np.float64)
+    kn, tf = to_dev(knots), to_dev(rgba)
+    prm = phantoms.render_params(lambda_g=0.6, lambda_k=0.4, kappa0=0.05, lambda_v=1.0, step_vox=0.25)
+    cams = [phantoms.ortho_camera(dims, sp, 30.0, 20.0, 24, 20), phantoms.persp_camera(dims, sp, 200.0, -35.0, 24, 20)]
+    cs = [dvr.camera_struct(c) for c in cams]
+    fs = dvr.features(v, sp, [1.0], c=0.1, layout=abi.DVR_SPLIT).without_bricks()
+    fq = dvr.features(v, sp, [1.0], c=0.1, layout=abi.DVR_QUAD).without_bricks()
+    a = dvr.render(v, fs, kn, tf, prm, cs)
+    b = dvr.render(v, fq, kn, tf, prm, cs)
+    torch.cuda.synchronize()
+    for x, y in zip(a, b):
+        np.testing.assert_array_equal(x.cpu().numpy(), y.cpu().numpy())
+    fn = feats_np(fq)
+    ref = oracle.render(v.cpu().numpy().astype(np.float64), fn, fn["gmax"], sp32(sp), knots, rgba,
+                        oracle_params(prm), cams)
+    img = b[0].cpu().numpy()
+    assert ref["rgba"][..., 3].max() > 0.05
+    for ch in range(4):
+        assert rel_err(img[..., ch], ref["rgba"][..., ch]) <= 1e-5
