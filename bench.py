@@ -39,6 +39,7 @@ RENDER_SOURCES = ["render.hip", "render_dev.hpp", "render_args.hpp", "common.hpp
 # estimate per voxel at three scales (stencils, eigenvalues, vesselness; see the design notes).
 FEAT_BYTES_F32 = 24
 FEAT_FLOP_3SCALE = 830
+FEAT_FLOP_1SCALE = 270
 
 
 def log(msg):
@@ -487,6 +488,23 @@ def leg_c5(dev, stream, dvr, torch, np, log):
         if it > 0:
             dt_.append(e0.elapsed_time(e1))
     tdn = float(np.median(dt_))
+    # the single-scale method on this large volume in FP32 (planar features: the compulsory 24 B/voxel,
+    # read I, write g, k, V; ~270 flop/voxel): the one configuration near the HBM ridge
+    v32 = dvr.normalize(raw, torch.float32)
+    f32 = dvr.alloc_features(tuple(raw.shape), w.spacing, torch.float32, abi.DVR_PLANAR, bricks=False)
+    ws32 = torch.empty(dvr.features_workspace_bytes(tuple(raw.shape), w.spacing, w.sigmas, c=w.c),
+                       dtype=torch.uint8, device=dev)
+    t32 = []
+    for it in range(4):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        dvr.features(v32, w.spacing, w.sigmas, c=w.c, eig_gap=1e-2, layout=abi.DVR_PLANAR, out=f32, ws=ws32)
+        e1.record(stream)
+        torch.cuda.synchronize()
+        if it > 0:
+            t32.append(e0.elapsed_time(e1))
+    tf32 = float(np.median(t32))
+    del v32, f32, ws32
     out = {"normalize_ms": float(t[0]), "features_ms": float(t[1]), "fwd_ms_per_view": float(t[2]) / 8,
            "bwd_ms_per_view": float(t[3]) / 8, "fwd_bwd_ms_per_view": float(t[2] + t[3]) / 8,
            "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3),
@@ -499,7 +517,11 @@ def leg_c5(dev, stream, dvr, torch, np, log):
            # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 32-bit operations per second
            "median3_ms": tdn, "median3_hbm_frac": 4 * raw.numel() / (tdn / 1e3) / (PEAK_HBM_GBS * 1e9),
            "median3_alu_frac": 388.0 * raw.numel() / (tdn / 1e3) / 3.93216e13,
-           "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9)}
+           "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "single_scale_fp32_features_ms": tf32,
+           "single_scale_fp32_features_voxels_per_s": raw.numel() / (tf32 / 1e3),
+           "single_scale_fp32_features_hbm_frac": FEAT_BYTES_F32 * raw.numel() / (tf32 / 1e3) / (PEAK_HBM_GBS * 1e9),
+           "single_scale_fp32_features_valu_frac": FEAT_FLOP_1SCALE * raw.numel() / (tf32 / 1e3) / (PEAK_FP32_TFLOPS * 1e12)}
     log(f"C5: normalize {t[0]:.2f} ms, features {t[1]:.2f} ms, fwd {t[2] / 8:.2f} ms/view, bwd {t[3] / 8:.2f} ms/view")
     return out
 
