@@ -148,3 +148,32 @@ def test_quad_render_tiny_grids(dims):
     assert ref["rgba"][..., 3].max() > 0.05
     for ch in range(4):
         assert rel_err(img[..., ch], ref["rgba"][..., ch]) <= 1e-5
+
+
+def test_head_fp16_quad_full_size_sampled():
+    """The FP16 leg as the benchmark times it: the head with FP16 quad-layout features (no brick
+    table), 1024^2 perspective views, against the oracle fed the same stored FP16 values (intensity
+    from the quads, g, k from the records, V from the V quads) on 4000 sampled pixels."""
+    w = phantoms.c2(1024, 1024, views=[0, 120, 250])
+    v16 = to_dev(w.vol, torch.float16)
+    f = dvr.features(v16, w.spacing, w.sigmas, c=w.c, dtype=torch.float16, layout=abi.DVR_QUAD).without_bricks()
+    kn, tf = to_dev(w.tf_knots), to_dev(w.tf_rgba)
+    img, T, k = dvr.render(None, f, kn, tf, w.params, [dvr.camera_struct(c) for c in w.cams])
+    torch.cuda.synchronize()
+    rec = f.grad.float().cpu().numpy().astype(np.float64)
+    feats = dict(g=np.ascontiguousarray(np.moveaxis(rec[..., 0:3], -1, 0)), kappa=rec[..., 3].copy(),
+                 V=f.ves.float().cpu().numpy().astype(np.float64)[..., 0].copy())
+    vin = f.iquad.float().cpu().numpy().astype(np.float64)[..., 0].copy()
+    np.testing.assert_array_equal(vin, v16.float().cpu().numpy())
+    rng = np.random.default_rng(16)
+    M = 4000
+    pix = np.stack([rng.integers(0, 3, M), rng.integers(0, 1024, M), rng.integers(0, 1024, M)], 1).astype(np.int32)
+    ref = oracle.render(vin, feats, float(f.gmax.item()), sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                        oracle_params(w.params), w.cams, pix=pix)
+    got = img.cpu().numpy()[pix[:, 0], pix[:, 2], pix[:, 1]].astype(np.float64)
+    et = f32(w.params["et_alpha"])
+    excl = np.abs(ref["T_last"] - (1 - et)) <= 1e-5 * (1 - et)
+    eb = [rel_err(got[~excl, ch], ref["rgba"][~excl, ch]) for ch in range(4)]
+    print(f"[quad fp16 head 1024^2] compute error vs oracle on the stored values: {['%.2e' % e for e in eb]}, "
+          f"ET-boundary rays excluded {int(excl.sum())}/{M}", flush=True)
+    assert max(eb) <= 1e-5 and excl.mean() < 1e-3
