@@ -61,7 +61,7 @@ typedef enum dvr_dtype { DVR_F32 = 0, DVR_F16 = 1, DVR_U16 = 2 } dvr_dtype;
  *                     (16 B in F32, 8 B in F16); ves = [nz][ny][nx]; kappa is unused; the intensity
  *                     is the volume, as in PLANAR.  A sample of zero extinction fetches only I; a
  *                     shaded one fetches I, one record and V per corner (the same 24 / 12 bytes per
- *                     voxel as PLANAR, in half the gathers).  Not supported by the batched launch.
+ *                     voxel as PLANAR, in half the gathers).
  *   DVR_QUAD:         grad = the SPLIT records, [nz][ny][nx][4] = (gx, gy, gz, kappa); ves =
  *                     [nz][ny][nx][4] vesselness quads (V(x,y,z), V(x,y+1,z), V(x,y,z+1),
  *                     V(x,y+1,z+1)), 0 past the last row or slice; iquad = the same quads of the

@@ -303,6 +303,8 @@ static hipError_t launch_batch_kernel(const BatchArgs &A, int layout, int dt, in
     DVR_B6(DVR_PLANAR, DVR_F16)
     DVR_B6(DVR_INTERLEAVED, DVR_F32)
     DVR_B6(DVR_INTERLEAVED, DVR_F16)
+    DVR_B6(DVR_SPLIT, DVR_F32)
+    DVR_B6(DVR_SPLIT, DVR_F16)
 #undef DVR_B6
 #undef DVR_B3
 #undef DVR_B
@@ -371,8 +373,8 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     if ((int64_t)d->nvol * (ns > 0 ? ns : 1) > kMaxVolScale)
         return fail(DVR_E_INVALID_ARG, "volumes x scales must not exceed %d", kMaxVolScale);
     const int layout = d->vols[0].feat.layout, fdt = d->vols[0].feat.dtype;
-    if (layout == DVR_SPLIT || layout == DVR_QUAD)
-        return fail(DVR_E_UNSUPPORTED, "the batched launch takes PLANAR or INTERLEAVED features");
+    if (layout == DVR_QUAD)
+        return fail(DVR_E_UNSUPPORTED, "the batched launch takes PLANAR, INTERLEAVED or SPLIT features");
     const int TX = kTXs[tune.xy_tile], TY = kTYs[tune.xy_tile];
 
     std::vector<BVol> vols(d->nvol);

@@ -70,12 +70,3 @@ def test_split_adjoint_matches_planar():
     (a1, b1), (a2, b2) = out
     assert np.linalg.norm(a1 - a2) <= 1e-6 * np.linalg.norm(a1)
     assert np.linalg.norm(b1 - b2) <= 1e-6 * np.linalg.norm(b1)
-
-
-def test_batch_rejects_split():
-    w = phantoms.c1(32, 32)
-    v = to_dev(w.vol)
-    f = dvr.alloc_features(tuple(v.shape), w.spacing, layout=abi.DVR_SPLIT)
-    view = (0, dvr.camera_struct(w.cams[0]), torch.empty((32, 32, 4), device="cuda"), None, None)
-    with pytest.raises(abi.DVRError):
-        dvr.Batch([v], [w.spacing], [f], [view], w.sigmas, to_dev(w.tf_knots), to_dev(w.tf_rgba), w.params, c=w.c)
