@@ -370,7 +370,10 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     ws = [phantoms.c4_volume(b, 512, 512) for b in range(nvol)]
     vols = [torch.from_numpy(w.vol).to(dev) for w in ws]
     sps = [w.spacing for w in ws]
-    feats = [dvr.alloc_features(tuple(v.shape), sp) for v, sp in zip(vols, sps)]
+    from paper_2605_19737_amd import _abi as abi_b
+    # split layout (I and V planes, one (gx, gy, gz, k) record per voxel) on both sides of the comparison
+    lay = abi_b.DVR_SPLIT
+    feats = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
     views = []
     for i, w in enumerate(ws):
         for cam in w.cams:
@@ -397,7 +400,7 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     # the same work as per-call launches (features per volume, then 4 views per volume), with counters
     cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     total = 0
-    pf = [dvr.alloc_features(tuple(v.shape), sp) for v, sp in zip(vols, sps)]
+    pf = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
     wsp = [torch.empty(dvr.features_workspace_bytes(tuple(v.shape), sp, ws[0].sigmas, c=ws[0].c), dtype=torch.uint8,
                        device=dev) for v, sp in zip(vols, sps)]
     imgs = [torch.empty((4, 512, 512, 4), dtype=torch.float32, device=dev) for _ in vols]
@@ -405,7 +408,7 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     def per_call(count):
         nonlocal total
         for i, (w, v, sp) in enumerate(zip(ws, vols, sps)):
-            dvr.features(v, sp, w.sigmas, c=w.c, out=pf[i], ws=wsp[i])
+            dvr.features(v, sp, w.sigmas, c=w.c, layout=lay, out=pf[i], ws=wsp[i])
             dvr.render(v, pf[i], knots, tf, w.params, [dvr.camera_struct(c) for c in w.cams], out=imgs[i],
                        counters=cnt if count else None)
             if count:
