@@ -69,8 +69,8 @@ typedef enum dvr_dtype { DVR_F32 = 0, DVR_F16 = 1, DVR_U16 = 2 } dvr_dtype;
  *                     must be the feature dtype); kappa is unused.  The 8 corners of a cell are the
  *                     quads of its two x-neighbours, so the raymarcher reads a cell's intensity, and
  *                     its V, in two loads instead of four (48 / 24 bytes per voxel).  dvr_render and
- *                     dvr_render_backward read the intensity from iquad and ignore vol.  Not supported
- *                     by the batched launch. */
+ *                     dvr_render_backward read the intensity from iquad and ignore vol.  The batched
+ *                     launch builds the quads itself, after each volume's last feature scale. */
 typedef enum dvr_layout { DVR_PLANAR = 0, DVR_INTERLEAVED = 1, DVR_SPLIT = 2, DVR_QUAD = 3 } dvr_layout;
 
 typedef struct dvr_grid {

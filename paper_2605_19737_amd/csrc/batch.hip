@@ -4,10 +4,12 @@
 // Work queue.  Items are taken in a fixed order from one atomic counter:
 //   Z  (volume, scale, slab of z slices): z filters of the slab into the volume's workspace;
 //   XY (volume, scale, 2-D tile, run of z slices): y/x filters, Hessian, eigenvalues, k, V, g;
+//   Q  (volume, slab of z slices; quad layout only): the V and intensity quads of the slab;
 //   RAY (view, 16x16 pixel tile): one ray per lane, front to back.
 // An XY item waits until every Z item of its (volume, scale) is done (and, for scale s > 0, every
 // XY item of scale s-1, whose vesselness it max-accumulates); a RAY item waits until every XY item
-// of its volume is done (features and |g|_max complete).  Completion is a per-(volume, scale)
+// of its volume is done (features and |g|_max complete; with quad-layout features, every Q item of
+// its volume, which itself waits for the volume's last XY scale).  Completion is a per-(volume, scale)
 // counter incremented after a device-scope release (every wave writes its L2 back); the waiter
 // polls, then acquires (invalidates its L2) once per volume per workgroup.  An item only waits for
 // items earlier in the queue, which were taken by running workgroups that never wait for later
@@ -34,15 +36,15 @@
 
 namespace dvr {
 
-enum { IT_Z = 0, IT_XY = 1, IT_RAY = 2 };
+enum { IT_Z = 0, IT_XY = 1, IT_RAY = 2, IT_Q = 3 };
 constexpr unsigned kMaxSpin = 1u << 23;  // polls of ~0.5 us: a wait gives up after several seconds
 constexpr int kMaxVolScale = 8192;       // volumes x scales per plan (LDS bitmaps of acquired counters)
 
 struct BItem {
     int32_t type_scale;  // type | scale << 8
-    int32_t v;           // volume (Z, XY) or view (RAY)
-    int32_t a;           // Z: first slice; XY: tile index; RAY: tile index
-    int32_t b;           // Z: end slice; XY: first slice of the run
+    int32_t v;           // volume (Z, XY, Q) or view (RAY)
+    int32_t a;           // Z, Q: first slice; XY: tile index; RAY: tile index
+    int32_t b;           // Z, Q: end slice; XY: first slice of the run
 };
 
 struct BVol {
@@ -50,6 +52,8 @@ struct BVol {
     void *grad, *kappa, *ves;
     float *gmax;
     float *ws;  // [nsigma][3][N] z-filtered fields
+    void *iquad;  // quad layout: the intensity quads
+    void *vtmp;   // quad layout: V as a plain field (features dtype) until the Q items build its quads
     int32_t n[3];
     int32_t tiles_x;
     double h[3];
@@ -78,6 +82,8 @@ struct BatchArgs {
     uint64_t taps;   // ScaleTaps[volume * ns + scale]
     unsigned *head, *zdone, *xydone, *err;
     const unsigned *nz_items, *nxy_items;
+    unsigned *qdone;           // per volume: Q items done (quad layout)
+    const unsigned *nq_items;  // per volume: Q items
     const unsigned *ray_need;  // count a ray tile waits for (= nxy_items, see the timeout test hook)
     unsigned max_spin;  // bound of every dependency wait (polls)
     float c, inv2a2, inv2b2, tau;
@@ -144,17 +150,40 @@ __device__ __forceinline__ void ray_pixel(int ray_tile, int tiles_x, int tile, i
     pj = ty * 16 + oy;
 }
 
+// Quads of slices [z0, z1) of one volume (the workgroup's 256 lanes over the slices' voxels):
+// dst[v] = (src(x,y,z), src(x,y+1,z), src(x,y,z+1), src(x,y+1,z+1)), 0 past the last row or slice,
+// as bit copies of the features dtype, for V (from the plain field) and for the intensity.
+template <typename T, typename T4>
+__device__ __forceinline__ void quads_slab(const T *__restrict__ src, T4 *__restrict__ dst, uint32_t nx, uint32_t ny,
+                                           uint32_t nz, int z0, int z1)
+{
+    const uint32_t plane = nx * ny;
+    const uint32_t end = (uint32_t)z1 * plane;
+    for (uint32_t v = (uint32_t)z0 * plane + threadIdx.x; v < end; v += 256u) {
+        const uint32_t row = v / nx, y = row % ny, z = row / ny;
+        const bool yi = y + 1u < ny, zi = z + 1u < nz;
+        T4 q;
+        q.x = src[v];
+        q.y = yi ? src[v + nx] : T(0);
+        q.z = zi ? src[v + plane] : T(0);
+        q.w = (yi && zi) ? src[v + plane + nx] : T(0);
+        dst[v] = q;
+    }
+}
+
 template <int LAYOUT, int DT, int KMAX, int TXY>
 __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
 {
     constexpr int TX = XYShape<TXY>::TX, TY = XYShape<TXY>::TY;
     extern __shared__ float lds[];
     __shared__ TFShared<KMAX> sh;
-    __shared__ unsigned acq_z[kMaxVolScale / 32], acq_xy[kMaxVolScale / 32];
+    __shared__ unsigned acq_z[kMaxVolScale / 32], acq_xy[kMaxVolScale / 32], acq_q[kMaxVolScale / 32];
+    // the quad layout computes its features as the split layout, with V into the volume's plain field
+    constexpr int FLAYOUT = (LAYOUT == DVR_QUAD) ? DVR_SPLIT : LAYOUT;
     __shared__ int item_sh;
     float kx[KMAX];
     tf_load<KMAX>(sh, kx, A.tf);
-    for (int i = threadIdx.x; i < kMaxVolScale / 32; i += 256) acq_z[i] = acq_xy[i] = 0u;
+    for (int i = threadIdx.x; i < kMaxVolScale / 32; i += 256) acq_z[i] = acq_xy[i] = acq_q[i] = 0u;
     __syncthreads();
     for (;;) {
         if (threadIdx.x == 0) item_sh = (int)atomicAdd(A.head, 1u);
@@ -194,7 +223,7 @@ __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
             a.vol = V.vol;
             a.grad = V.grad;
             a.kappa = V.kappa;
-            a.ves = V.ves;
+            a.ves = (LAYOUT == DVR_QUAD) ? V.vtmp : V.ves;
             a.gmax = V.gmax;
             a.fro = nullptr;
             a.nx = V.n[0];
@@ -214,21 +243,41 @@ __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
             const int z1 = min(w.b + A.zrun, V.n[2]);
             float vmax = 0.f;
             for (int z = w.b; z < z1; ++z)
-                vmax = fmaxf(vmax, xy_tile<DT, DT, LAYOUT, TX, TY>(a, taps, bx * TX, by * TY, z, lds));
+                vmax = fmaxf(vmax, xy_tile<DT, DT, FLAYOUT, TX, TY>(a, taps, bx * TX, by * TY, z, lds));
             if (s == 0) {
                 vmax = wave_max(vmax);
                 if ((threadIdx.x & 63) == 0) atomic_max_pos(V.gmax, vmax);
             }
             release_done(A.xydone + vs);
+        } else if (type == IT_Q) {
+            if constexpr (LAYOUT == DVR_QUAD) {
+                const int vs = w.v * A.ns + A.ns - 1;
+                wait_for(A.xydone + vs, A.nxy_items[vs], A.err, acq_xy, vs, A.max_spin);
+                __syncthreads();
+                const auto &V = vols[w.v];
+                const uint32_t nx = (uint32_t)V.n[0], ny = (uint32_t)V.n[1], nz = (uint32_t)V.n[2];
+                if constexpr (DT == DVR_F32) {
+                    quads_slab(static_cast<const uint32_t *>(V.vtmp), static_cast<uint4 *>(V.ves), nx, ny, nz, w.a, w.b);
+                    quads_slab(static_cast<const uint32_t *>(V.vol), static_cast<uint4 *>(V.iquad), nx, ny, nz, w.a, w.b);
+                } else {
+                    quads_slab(static_cast<const uint16_t *>(V.vtmp), static_cast<ushort4 *>(V.ves), nx, ny, nz, w.a, w.b);
+                    quads_slab(static_cast<const uint16_t *>(V.vol), static_cast<ushort4 *>(V.iquad), nx, ny, nz, w.a,
+                               w.b);
+                }
+                release_done(A.qdone + w.v);
+            }
         } else {
             const auto &Vw = views[w.v];
             const int vol = Vw.vol;
             const int vs = vol * A.ns + A.ns - 1;
-            wait_for(A.xydone + vs, A.ray_need[vs], A.err, acq_xy, vs, A.max_spin);
+            if constexpr (LAYOUT == DVR_QUAD)
+                wait_for(A.qdone + vol, A.nq_items[vol], A.err, acq_q, vol, A.max_spin);
+            else
+                wait_for(A.xydone + vs, A.ray_need[vs], A.err, acq_xy, vs, A.max_spin);
             __syncthreads();
             const auto &V = vols[vol];
             KFeat f;
-            f.vol = V.vol;
+            f.vol = (LAYOUT == DVR_QUAD) ? V.iquad : V.vol;
             f.grad = V.grad;
             f.kappa = V.kappa;
             f.ves = V.ves;
@@ -283,7 +332,10 @@ __global__ void k_batch_init(BatchArgs A, int nvs, int nvol)
         else A.xydone[i - 2 - nvs] = 0u;
     }
     const BVol *vols = (const BVol *)A.vols;
-    for (int v = threadIdx.x; v < nvol; v += blockDim.x) *vols[v].gmax = 0.f;
+    for (int v = threadIdx.x; v < nvol; v += blockDim.x) {
+        *vols[v].gmax = 0.f;
+        A.qdone[v] = 0u;
+    }
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -305,6 +357,8 @@ static hipError_t launch_batch_kernel(const BatchArgs &A, int layout, int dt, in
     DVR_B6(DVR_INTERLEAVED, DVR_F16)
     DVR_B6(DVR_SPLIT, DVR_F32)
     DVR_B6(DVR_SPLIT, DVR_F16)
+    DVR_B6(DVR_QUAD, DVR_F32)
+    DVR_B6(DVR_QUAD, DVR_F16)
 #undef DVR_B6
 #undef DVR_B3
 #undef DVR_B
@@ -373,8 +427,6 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     if ((int64_t)d->nvol * (ns > 0 ? ns : 1) > kMaxVolScale)
         return fail(DVR_E_INVALID_ARG, "volumes x scales must not exceed %d", kMaxVolScale);
     const int layout = d->vols[0].feat.layout, fdt = d->vols[0].feat.dtype;
-    if (layout == DVR_QUAD)
-        return fail(DVR_E_UNSUPPORTED, "the batched launch takes PLANAR, INTERLEAVED or SPLIT features");
     const int TX = kTXs[tune.xy_tile], TY = kTYs[tune.xy_tile];
 
     std::vector<BVol> vols(d->nvol);
@@ -398,6 +450,8 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
         B.kappa = bv.feat.kappa;
         B.ves = bv.feat.ves;
         B.gmax = bv.feat.gmax;
+        B.iquad = bv.feat.iquad;
+        B.vtmp = nullptr;
         B.n[0] = bv.grid.nx;
         B.n[1] = bv.grid.ny;
         B.n[2] = bv.grid.nz;
@@ -414,6 +468,7 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
             lds_floats = std::max(lds_floats, (size_t)(3 * (TY + 2 * t.ax[1].R) + 6 * TY) * (size_t)(TX + 2 * t.ax[0].R));
         }
         ws_total += (size_t)ns * 12u * (size_t)nvox(&bv.grid);
+        if (layout == DVR_QUAD) ws_total += ((size_t)4u * (size_t)nvox(&bv.grid) + 255u) & ~(size_t)255u;
     }
     if (lds_floats * 4 > 60 * 1024)
         return fail(DVR_E_UNSUPPORTED, "feature tile with halo needs %zu bytes of LDS (limit 60 KB)", lds_floats * 4);
@@ -455,6 +510,13 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
                     nxy_items[(size_t)v * ns + sc]++;
                 }
         }
+    std::vector<unsigned> nq_items((size_t)d->nvol, 0u);
+    if (layout == DVR_QUAD)
+        for (int v = 0; v < d->nvol; ++v)
+            for (int z = 0; z < vols[v].n[2]; z += tune.z_chunk) {
+                items.push_back({IT_Q, v, z, std::min(z + tune.z_chunk, vols[v].n[2])});
+                nq_items[v]++;
+            }
     for (int w = 0; w < d->nview; ++w) {
         const int nt = views[w].tiles_x * ((views[w].H + 15) / 16);
         for (int t = 0; t < nt; ++t) items.push_back({IT_RAY, w, t, 0});
@@ -475,7 +537,7 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     BVol *d_vols = (BVol *)dalloc(sizeof(BVol) * vols.size());
     BView *d_views = (BView *)dalloc(sizeof(BView) * std::max<size_t>(views.size(), 1));
     ScaleTaps *d_taps = (ScaleTaps *)dalloc(sizeof(ScaleTaps) * taps.size());
-    unsigned *d_ctr = (unsigned *)dalloc(sizeof(unsigned) * (size_t)(2 + 5 * nvs));
+    unsigned *d_ctr = (unsigned *)dalloc(sizeof(unsigned) * (size_t)(2 + 5 * nvs + 2 * d->nvol));
     float *d_ws = (float *)dalloc(ws_total);
     if (!d_items || !d_vols || !d_views || !d_taps || !d_ctr || !d_ws) {
         plan_free(P);
@@ -485,6 +547,10 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     for (int v = 0; v < d->nvol; ++v) {
         vols[v].ws = d_ws + off / 4;
         off += (size_t)ns * 12u * (size_t)nvox(&d->vols[v].grid);
+        if (layout == DVR_QUAD) {
+            vols[v].vtmp = d_ws + off / 4;
+            off += ((size_t)4u * (size_t)nvox(&d->vols[v].grid) + 255u) & ~(size_t)255u;
+        }
     }
     BatchArgs A;
     memset(&A, 0, sizeof A);
@@ -505,6 +571,9 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     A.nxy_items = d_nxy;
     unsigned *d_need = d_ctr + 2 + 4 * nvs;
     A.ray_need = d_need;
+    A.qdone = d_ctr + 2 + 5 * nvs;
+    unsigned *d_nq = d_ctr + 2 + 5 * nvs + d->nvol;
+    A.nq_items = d_nq;
     A.max_spin = kMaxSpin;
     // Test hook (DVR_BATCH_TEST_TIMEOUT=1): the rays of volume 0 wait for one feature item more than
     // exist, with a short bound, so the launch exercises the timeout path and still exits normally.
@@ -541,6 +610,7 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
     if (e == hipSuccess) e = hipMemcpy(d_nz, nz_items.data(), sizeof(unsigned) * nvs, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_nxy, nxy_items.data(), sizeof(unsigned) * nvs, hipMemcpyHostToDevice);
     if (e == hipSuccess) e = hipMemcpy(d_need, need.data(), sizeof(unsigned) * nvs, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(d_nq, nq_items.data(), sizeof(unsigned) * d->nvol, hipMemcpyHostToDevice);
     int dev = 0, ncu = 0;
     if (e == hipSuccess) e = hipGetDevice(&dev);
     if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);

@@ -51,6 +51,8 @@ def _assert_equal(feats, views, ref_f, ref_v):
             assert torch.equal(a.kappa, b.kappa)
         if a.ves is not None:
             assert torch.equal(a.ves, b.ves)
+        if a.iquad is not None:
+            assert torch.equal(a.iquad, b.iquad)
         assert torch.equal(a.gmax, b.gmax)
     for (i, cam, img, T, k), (rimg, rT, rk) in zip(views, ref_v):
         assert torch.equal(img, rimg[0]) and torch.equal(T, rT[0]) and torch.equal(k, rk[0])
@@ -75,15 +77,18 @@ def test_batch_equals_standalone(tune):
     b.close()
 
 
-@pytest.mark.parametrize("dtype", [torch.float32, torch.float16])
-def test_batch_split_equals_standalone(dtype):
-    """The split layout (I and V planes, (gx, gy, gz, k) records) in the batched launch, two scales."""
-    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=3, layout=abi.DVR_SPLIT, dtype=dtype,
+@pytest.mark.parametrize("layout,dtype", [(abi.DVR_SPLIT, torch.float32), (abi.DVR_SPLIT, torch.float16),
+                                          (abi.DVR_QUAD, torch.float32), (abi.DVR_QUAD, torch.float16)])
+def test_batch_split_and_quad_equal_standalone(layout, dtype):
+    """The split layout (I and V planes, (gx, gy, gz, k) records) and the quad layout (whose V and
+    intensity quads the launch builds in Q items after each volume's last scale) in the batched
+    launch, two scales."""
+    ws, vols, spacings, feats, views, knots, rgba, sig = _scene(nvol=3, layout=layout, dtype=dtype,
                                                                 sigmas=(1.0, 2.0))
     b = dvr.Batch(vols, spacings, feats, views, sig, knots, rgba, ws[0].params, c=ws[0].c)
     b.launch()
     b.check()
-    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, abi.DVR_SPLIT, dtype)
+    ref_f, ref_v = _standalone(ws, vols, spacings, views, knots, rgba, sig, layout, dtype)
     torch.cuda.synchronize()
     _assert_equal(feats, views, ref_f, ref_v)
     b.launch()

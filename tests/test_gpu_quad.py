@@ -104,15 +104,6 @@ def test_quad_adjoint_matches_split(dtype):
           f"|dfeat| {np.linalg.norm(out[1][5]):.3e} match the split layout", flush=True)
 
 
-def test_batch_rejects_quad():
-    w = phantoms.c1(32, 32)
-    v = to_dev(w.vol)
-    f = dvr.alloc_features(tuple(v.shape), w.spacing, layout=abi.DVR_QUAD)
-    view = (0, dvr.camera_struct(w.cams[0]), torch.empty((32, 32, 4), device="cuda"), None, None)
-    with pytest.raises(abi.DVRError):
-        dvr.Batch([v], [w.spacing], [f], [view], w.sigmas, to_dev(w.tf_knots), to_dev(w.tf_rgba), w.params, c=w.c)
-
-
 def test_quad_needs_matching_volume_dtype():
     w = phantoms.c1(32, 32)
     v = to_dev(w.vol)
