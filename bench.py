@@ -371,7 +371,8 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     vols = [torch.from_numpy(w.vol).to(dev) for w in ws]
     sps = [w.spacing for w in ws]
     from paper_2605_19737_amd import _abi as abi_b
-    # split layout (I and V planes, one (gx, gy, gz, k) record per voxel) on both sides of the comparison
+    # split layout on both sides of the comparison (on these small thick-slice volumes the quad layout's
+    # extra quad-building step costs the batched launch more than its two-load corners save: 85.8 vs 83.1 ms)
     lay = abi_b.DVR_SPLIT
     feats = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
     views = []
