@@ -680,6 +680,10 @@ struct DWinT {
     static constexpr int kVox = W0 * W1 * W2;      // voxels of the window
     static constexpr int kEntries = kVox * CH;     // doubles in LDS
     static_assert(kVox % 64 == 0, "whole flush rounds");
+    // entries are stored bank-swizzled: bits 1-3 of the index XOR bits 5-7, an involution within each
+    // aligned block of 32, so that entries 32, 64, ... apart (neighbouring voxels along the window's
+    // outer ranks, which the lanes of a wave add to in one instruction) fall in different LDS banks
+    __device__ __forceinline__ static int swz(int e) { return e ^ (((e >> 5) & 7) << 1); }
     double *w;    // this wave's kEntries in LDS: [channel][voxel u0 + W0 (u1 + W1 u2)] (channel-major:
                   // lanes on neighbouring voxels of one channel fall in different banks)
     int o[3];     // voxel index (x, y, z) of the window's first entry; wave-uniform
@@ -729,10 +733,10 @@ struct DWinT {
             const int gi = olin + u0 * gst[0] + u1 * gst[1] + u2 * gst[2];
 #pragma unroll
             for (int c = 0; c < CH; ++c) {
-                const double v = w[c * kVox + e];
+                const double v = w[c * kVox + swz(e)];
                 if (v != 0.0) {
                     atomicAdd(c == 0 ? dvol + gi : dfeat + (size_t)(c - 1) * N + gi, (float)v);
-                    w[c * kVox + e] = 0.0;
+                    w[c * kVox + swz(e)] = 0.0;
                 }
             }
         }
@@ -845,7 +849,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 const int b = dw.index(acell);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    double *p = win + (b + dw.crn[e]);
+                    double *p = win + DWinF::swz(b + dw.crn[e]);
 #pragma unroll
                     for (int ch6 = 0; ch6 < 6; ++ch6)
                         if (acc[e * 6 + ch6] != 0.f)
@@ -1001,7 +1005,7 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
                     // wave scope: only this wave touches its window
-                    __hip_atomic_fetch_add(win + b + dw.crn[e], (double)cw[e], __ATOMIC_RELAXED,
+                    __hip_atomic_fetch_add(win + DWin::swz(b + dw.crn[e]), (double)cw[e], __ATOMIC_RELAXED,
                                            __HIP_MEMORY_SCOPE_WAVEFRONT);
                 }
             } else if (need) {
