@@ -849,12 +849,25 @@ __device__ __forceinline__ void march_bwd(const KFeat &feat, const KGrid &g, con
                 const int b = dw.index(acell);
 #pragma unroll
                 for (int e = 0; e < 8; ++e) {
-                    double *p = win + DWinF::swz(b + dw.crn[e]);
+                    // the four lanes of a 2 x 2 pixel quad emit the corners in different orders (corner
+                    // e XOR 0, 7, 3, 4): rays of one cell then add to different entries in each
+                    // instruction.  Selected with bit masks, which keep the register sums out of scratch.
+                    const int c0 = (threadIdx.x & 1u) ? -1 : 0, c1 = (threadIdx.x & 2u) ? -1 : 0;
+                    const uint32_t m0 = (uint32_t)c0, m1 = (uint32_t)c1;
+                    const int e7 = e ^ 7, e3 = e ^ 3, e4 = e ^ 4;
+                    const int ca = (dw.crn[e] & ~c0) | (dw.crn[e7] & c0), cb = (dw.crn[e3] & ~c0) | (dw.crn[e4] & c0);
+                    double *p = win + DWinF::swz(b + ((ca & ~c1) | (cb & c1)));
 #pragma unroll
-                    for (int ch6 = 0; ch6 < 6; ++ch6)
-                        if (acc[e * 6 + ch6] != 0.f)
-                            __hip_atomic_fetch_add(p + ch6 * DWinF::kVox, (double)acc[e * 6 + ch6], __ATOMIC_RELAXED,
+                    for (int ch6 = 0; ch6 < 6; ++ch6) {
+                        const uint32_t va = (__builtin_bit_cast(uint32_t, acc[e * 6 + ch6]) & ~m0) |
+                                            (__builtin_bit_cast(uint32_t, acc[e7 * 6 + ch6]) & m0);
+                        const uint32_t vb = (__builtin_bit_cast(uint32_t, acc[e3 * 6 + ch6]) & ~m0) |
+                                            (__builtin_bit_cast(uint32_t, acc[e4 * 6 + ch6]) & m0);
+                        const float val = __builtin_bit_cast(float, (va & ~m1) | (vb & m1));
+                        if (val != 0.f)
+                            __hip_atomic_fetch_add(p + ch6 * DWinF::kVox, (double)val, __ATOMIC_RELAXED,
                                                    __HIP_MEMORY_SCOPE_WAVEFRONT);
+                    }
                 }
             } else if (flag) {
                 const uint32_t nx = (uint32_t)g.n[0], plane = nx * (uint32_t)g.n[1];
