@@ -77,6 +77,33 @@ def test_render_feature_grads_match_oracle(layout, dtype, K):
     assert _nerr(dvol.cpu().numpy(), dvol0.cpu().numpy()) <= 1e-6
 
 
+def test_render_feature_grads_ragged_quad():
+    """Quad layout, perspective and orthographic views of 37 x 29 pixels: tiles and 2 x 2 lane quads
+    cut by the image edge (lanes without a ray), against the oracle's reverse mode."""
+    w = _diff_scene()
+    w.cams = [phantoms.ortho_camera(w.dims, w.spacing, 50.0, 25.0, 37, 29),
+              phantoms.persp_camera(w.dims, w.spacing, 200.0, -20.0, 37, 29)]
+    dv = to_dev(w.vol)
+    f = dvr.features(dv, w.spacing, w.sigmas, c=w.c, layout=abi.DVR_QUAD)
+    kn, rg = tf_dev(w)
+    img, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    rng = np.random.default_rng(12)
+    dout = to_dev(rng.normal(size=tuple(img.shape)))
+    dtf, dvol, fg = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, dout, want_features=True)
+    torch.cuda.synchronize()
+    fn = feats_np(f)
+    I = dv.cpu().numpy().astype(np.float64)
+    rtf, rI, rfg = oracle.render_vjp(I, fn, fn["gmax"], sp32(w.spacing), w.tf_knots, w.tf_rgba,
+                                     oracle_params(w.params), w.cams, dout.cpu().numpy(), want_features=True)
+    errs = {key: _nerr(fg[key].cpu().numpy(), rfg[key]) for key in ("g", "kappa", "V")}
+    errs["gmax"] = abs(float(fg["gmax"].item()) - rfg["gmax"]) / abs(rfg["gmax"])
+    errs["tf"] = _nerr(dtf.cpu().numpy(), rtf)
+    near = bf.near_knot_voxels(I.shape, sp32(w.spacing), I, w.tf_knots, w.params, w.cams)
+    errs["I"] = _nerr(dvol.cpu().numpy()[~near], rI[~near])
+    print("[render feature grads, ragged quad] " + " ".join(f"{k}={v:.2e}" for k, v in errs.items()), flush=True)
+    assert all(v <= 1e-4 for v in errs.values()), errs
+
+
 def _tie_free_upstream(I, spacing, sigmas, fr, seed, tie=1e-4):
     """Random upstream gradients; no V upstream where two scales' V are within tie of each other
     (relative) or where V is 0; the |g| maximum made unique by the caller's input."""
