@@ -242,10 +242,11 @@ typedef _Float16 f16x2 __attribute__((ext_vector_type(2)));
 // apart) often stay in the same cell, and then no gather is issued for that lane.  Planar
 // layouts load the intensity corners first and the feature corners only for a sample whose
 // extinction is non-zero; an interleaved record brings all six channels in one load per corner
-// (F32: 16 + 8 bytes, F16: 12 bytes kept packed and widened at use).
+// (F32: 16 + 8 bytes, F16: 12 bytes kept packed and widened at use).  F16 quad-layout corners are
+// kept packed the same way, (I, gx), (gy, gz), (k, V) per corner, and widened at use.
 template <int LAYOUT, int DT>
 struct CornerCache {
-    static constexpr bool kPacked = (LAYOUT == DVR_INTERLEAVED && DT == DVR_F16);
+    static constexpr bool kPacked = (LAYOUT == DVR_INTERLEAVED || LAYOUT == DVR_QUAD) && DT == DVR_F16;
     uint32_t base;  // byte offset of the cached cell's first corner, or ~0
     bool feat;      // feature corners valid for this cell
     float v[kPacked ? 1 : 8][6];
@@ -279,6 +280,14 @@ struct CornerCache {
     {
         if (c.off[0] == base) return;
         base = c.off[0];
+        if constexpr (LAYOUT == DVR_QUAD && DT == DVR_F16) {
+            // the 8 intensity halves into the low halves of the packed words (I, gx)
+            const u32x4 a = ld4(vx.b[0], c.off[0] << 2);
+            raw[0][0] = a.x; raw[2][0] = a.x >> 16; raw[4][0] = a.y; raw[6][0] = a.y >> 16;
+            raw[1][0] = a.z; raw[3][0] = a.z >> 16; raw[5][0] = a.w; raw[7][0] = a.w >> 16;
+            feat = false;
+            return;
+        }
         if constexpr (LAYOUT == DVR_QUAD) {
             quad_pair<0>(vx.b[0], c.off[0] << 2);
             feat = false;
@@ -346,6 +355,23 @@ struct CornerCache {
                     if constexpr (DT == DVR_F32) v[e][ch] = ldf(vx.b[ch], off);
                     else v[e][ch] = ldh(vx.b[ch], off);
                 }
+            }
+        } else if constexpr (LAYOUT == DVR_QUAD && DT == DVR_F16) {
+            if (feat) return;
+            feat = true;
+            const u32x4 vq = ld4(vx.b[2], c.off[0] << 2);
+            const uint32_t V[8] = {vq.x & 0xffffu, vq.z & 0xffffu, vq.x >> 16, vq.z >> 16,
+                                   vq.y & 0xffffu, vq.w & 0xffffu, vq.y >> 16, vq.w >> 16};
+#pragma unroll
+            for (int j = 0; j < 4; ++j) {
+                const u32x4 r = ld4(vx.b[1], c.off[j] << 2);  // records of corners 2j (x) and 2j + 1 (x + 1)
+                const int e0 = 2 * j, e1 = 2 * j + 1;
+                raw[e0][0] = (raw[e0][0] & 0xffffu) | (r.x << 16);
+                raw[e0][1] = (r.x >> 16) | (r.y << 16);
+                raw[e0][2] = (r.y >> 16) | (V[e0] << 16);
+                raw[e1][0] = (raw[e1][0] & 0xffffu) | (r.z << 16);
+                raw[e1][1] = (r.z >> 16) | (r.w << 16);
+                raw[e1][2] = (r.w >> 16) | (V[e1] << 16);
             }
         } else if constexpr (LAYOUT == DVR_SPLIT || LAYOUT == DVR_QUAD) {
             if (feat) return;
