@@ -14,7 +14,7 @@
 //      first scale, and at the voxel's winning scale dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T from
 //      a Jacobi eigen-decomposition; at the first scale it also writes dL/dg + dL/dk dk/dg and
 //      the arg-max key of |g|;
-//   2. k_tx, k_ty, k_tz apply the transposed x, y and z operators (the forward's z-then-y-then-x
+//   2. k_tx, k_ty_run, k_tz_run apply the transposed x, y and z operators (the forward's z-then-y-then-x
 //      order reversed: six fields after x, three after y, one accumulated into dL/dI after z).
 // Last, dL/d|g|_max goes to the arg-max voxel's gradient (k_fb_gmax) and the transposed central
 // difference of the gradient is added (k_fb_gradT).
@@ -365,59 +365,94 @@ __global__ __launch_bounds__(256) void k_tx_lds(const float *__restrict__ Hb, fl
     for (int k = 0; k < 6; ++k) X[(size_t)k * N + o] = acc[k];
 }
 
+// y and z: each lane walks a run of kTRun consecutive outputs along the axis at one position of the
+// other two (k_ty_run: blockIdx.y = run, blockIdx.z = z; k_tz_run: blockIdx.y = run), so every input
+// row along the axis is loaded once per run rather than once per output it reaches (2R + 1 times:
+// those re-reads through the caches bound a one-output-per-lane form).  Each output sums the rows i
+// of its band in ascending order.  The band-table reads are uniform over the workgroup.
+//
 // y: the three z-groups: Y0 = G^T X_xx + (D2 G)^T X_yy + (D1 G)^T X_xy (z operator G),
 // Y1 = G^T X_xz + (D1 G)^T X_yz (z operator D1 G), Y2 = G^T X_zz (z operator D2 G)
-__global__ __launch_bounds__(256) void k_ty(const float *__restrict__ X, float *__restrict__ Y,
-                                            const float *__restrict__ B, int nx, int ny, int nz, int R)
+constexpr int kTyRun = 8, kTzRun = 4;
+template <int kTRun>
+__global__ __launch_bounds__(64) void k_ty_run(const float *__restrict__ X, float *__restrict__ Y,
+                                               const float *__restrict__ B, int nx, int ny, int nz, int R)
 {
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
-    if (e >= plane) return;
-    const int z = (int)blockIdx.y;
-    const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
-    const size_t N = (size_t)plane * (size_t)nz;
+    const int x = (int)(blockIdx.x * 64u + threadIdx.x);
+    if (x >= nx) return;
+    const int yb = (int)blockIdx.y * kTRun, z = (int)blockIdx.z;
+    const int nq = min(kTRun, ny - yb);
+    const size_t plane = (size_t)nx * (size_t)ny, N = plane * (size_t)nz;
     const size_t col = (size_t)z * plane + (size_t)x;
     const int W = 2 * R + 1;
-    float y0 = 0.f, y1 = 0.f, y2 = 0.f;
-    const int i0 = max(0, y - R), i1 = min(ny - 1, y + R);
+    float y0[kTRun], y1[kTRun], y2[kTRun];
+#pragma unroll
+    for (int q = 0; q < kTRun; ++q) y0[q] = y1[q] = y2[q] = 0.f;
+    const int i0 = max(0, yb - R), i1 = min(ny - 1, yb + nq - 1 + R);
     for (int i = i0; i <= i1; ++i) {
-        const int d = y - i + R;
-        const float b0 = B[(size_t)d * ny + i], b1 = B[(size_t)(W + d) * ny + i], b2 = B[(size_t)(2 * W + d) * ny + i];
         const size_t sidx = col + (size_t)i * nx;
-        y0 = fmaf(b0, X[sidx], y0);
-        y0 = fmaf(b2, X[N + sidx], y0);
-        y0 = fmaf(b1, X[3 * N + sidx], y0);
-        y1 = fmaf(b0, X[4 * N + sidx], y1);
-        y1 = fmaf(b1, X[5 * N + sidx], y1);
-        y2 = fmaf(b0, X[2 * N + sidx], y2);
+        const float x0 = X[sidx], x1 = X[N + sidx], x2 = X[2 * N + sidx];
+        const float x3 = X[3 * N + sidx], x4 = X[4 * N + sidx], x5 = X[5 * N + sidx];
+#pragma unroll
+        for (int q = 0; q < kTRun; ++q) {
+            const int d = yb + q - i + R;
+            if (q < nq && d >= 0 && d < W) {
+                const float b0 = B[(size_t)d * ny + i], b1 = B[(size_t)(W + d) * ny + i];
+                const float b2 = B[(size_t)(2 * W + d) * ny + i];
+                y0[q] = fmaf(b0, x0, y0[q]);
+                y0[q] = fmaf(b2, x1, y0[q]);
+                y0[q] = fmaf(b1, x3, y0[q]);
+                y1[q] = fmaf(b0, x4, y1[q]);
+                y1[q] = fmaf(b1, x5, y1[q]);
+                y2[q] = fmaf(b0, x2, y2[q]);
+            }
+        }
     }
-    const size_t o = col + (size_t)y * nx;
-    Y[o] = y0;
-    Y[N + o] = y1;
-    Y[2 * N + o] = y2;
+#pragma unroll
+    for (int q = 0; q < kTRun; ++q) {
+        if (q < nq) {
+            const size_t o = col + (size_t)(yb + q) * nx;
+            Y[o] = y0[q];
+            Y[N + o] = y1[q];
+            Y[2 * N + o] = y2[q];
+        }
+    }
 }
 
 // z: dL/dI += G^T Y0 + (D1 G)^T Y1 + (D2 G)^T Y2 along z
-__global__ __launch_bounds__(256) void k_tz(const float *__restrict__ Y, float *__restrict__ dvol,
-                                            const float *__restrict__ B, int nx, int ny, int nz, int R)
+template <int kTRun>
+__global__ __launch_bounds__(64) void k_tz_run(const float *__restrict__ Y, float *__restrict__ dvol,
+                                               const float *__restrict__ B, int nx, int ny, int nz, int R)
 {
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const size_t e = (size_t)blockIdx.x * 64u + threadIdx.x;
     if (e >= plane) return;
-    const int z = (int)blockIdx.y;
-    const size_t N = (size_t)plane * (size_t)nz;
+    const int zb = (int)blockIdx.y * kTRun;
+    const int nq = min(kTRun, nz - zb);
+    const size_t N = plane * (size_t)nz;
     const int W = 2 * R + 1;
-    float acc = 0.f;
-    const int i0 = max(0, z - R), i1 = min(nz - 1, z + R);
+    float acc[kTRun];
+#pragma unroll
+    for (int q = 0; q < kTRun; ++q) acc[q] = 0.f;
+    const int i0 = max(0, zb - R), i1 = min(nz - 1, zb + nq - 1 + R);
     for (int i = i0; i <= i1; ++i) {
-        const int d = z - i + R;
-        const float b0 = B[(size_t)d * nz + i], b1 = B[(size_t)(W + d) * nz + i], b2 = B[(size_t)(2 * W + d) * nz + i];
         const size_t sidx = (size_t)i * plane + e;
-        acc = fmaf(b0, Y[sidx], acc);
-        acc = fmaf(b1, Y[N + sidx], acc);
-        acc = fmaf(b2, Y[2 * N + sidx], acc);
+        const float v0 = Y[sidx], v1 = Y[N + sidx], v2 = Y[2 * N + sidx];
+#pragma unroll
+        for (int q = 0; q < kTRun; ++q) {
+            const int d = zb + q - i + R;
+            if (q < nq && d >= 0 && d < W) {
+                const float b0 = B[(size_t)d * nz + i], b1 = B[(size_t)(W + d) * nz + i];
+                const float b2 = B[(size_t)(2 * W + d) * nz + i];
+                acc[q] = fmaf(b0, v0, acc[q]);
+                acc[q] = fmaf(b1, v1, acc[q]);
+                acc[q] = fmaf(b2, v2, acc[q]);
+            }
+        }
     }
-    dvol[(size_t)z * plane + e] += acc;
+#pragma unroll
+    for (int q = 0; q < kTRun; ++q)
+        if (q < nq) dvol[(size_t)(zb + q) * plane + e] += acc[q];
 }
 
 // dL/d|g|_max to the arg-max voxel's gradient: d|g|/dg = g / |g|
@@ -545,6 +580,8 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
     const uint32_t N = plane * (uint32_t)g.nz;
     const dim3 pgrid((plane + 255) / 256, g.nz);
+    const dim3 tygrid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kTyRun - 1) / kTyRun), (unsigned)g.nz);
+    const dim3 tzgrid((unsigned)((plane + 63) / 64), (unsigned)((g.nz + kTzRun - 1) / kTzRun));
     const dim3 vgrid((N + 255) / 256);
     hipError_t e;
     // band tables of every scale and axis (one launch per scale)
@@ -593,8 +630,8 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
                                bt[s][0], p.taps[s].ax[0], g.nx, g.ny, g.nz);
         else
             hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
-        hipLaunchKernelGGL(k_ty, pgrid, dim3(256), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
-        hipLaunchKernelGGL(k_tz, pgrid, dim3(256), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
+        hipLaunchKernelGGL(k_ty_run<kTyRun>, tygrid, dim3(64), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
+        hipLaunchKernelGGL(k_tz_run<kTzRun>, tzgrid, dim3(64), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (vol_dt == DVR_F32)
