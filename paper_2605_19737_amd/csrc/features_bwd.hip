@@ -389,6 +389,7 @@ __global__ __launch_bounds__(64) void k_ty_run(const float *__restrict__ X, floa
 #pragma unroll
     for (int q = 0; q < kTRun; ++q) y0[q] = y1[q] = y2[q] = 0.f;
     const int i0 = max(0, yb - R), i1 = min(ny - 1, yb + nq - 1 + R);
+#pragma unroll 2
     for (int i = i0; i <= i1; ++i) {
         const size_t sidx = col + (size_t)i * nx;
         const float x0 = X[sidx], x1 = X[N + sidx], x2 = X[2 * N + sidx];
@@ -435,6 +436,7 @@ __global__ __launch_bounds__(64) void k_tz_run(const float *__restrict__ Y, floa
 #pragma unroll
     for (int q = 0; q < kTRun; ++q) acc[q] = 0.f;
     const int i0 = max(0, zb - R), i1 = min(nz - 1, zb + nq - 1 + R);
+#pragma unroll 4
     for (int i = i0; i <= i1; ++i) {
         const size_t sidx = (size_t)i * plane + e;
         const float v0 = Y[sidx], v1 = Y[N + sidx], v2 = Y[2 * N + sidx];
