@@ -365,6 +365,78 @@ __global__ __launch_bounds__(256) void k_tx_lds(const float *__restrict__ Hb, fl
     for (int k = 0; k < 6; ++k) X[(size_t)k * N + o] = acc[k];
 }
 
+// Fixed-radius form of k_tx_lds for the radii of the forward's fixed-radius kernels: an interior
+// output unrolls its 2R + 1 taps (offset m = x - i from R down to -R: the rows in ascending order),
+// so its weights are compile-time-indexed kernel arguments held in scalar registers and its LDS
+// reads take immediate offsets; the others loop over the band table as k_tx_lds does.  The same
+// products in the same order: the same bits.
+template <int R>
+__global__ __launch_bounds__(256) void k_tx_lds_r(const float *__restrict__ Hb, float *__restrict__ X,
+                                                  const float *__restrict__ B, AxisTaps t, int nx, int ny, int nz)
+{
+    __shared__ float s[6][kTxChunk + 2 * (R + 1)];
+    constexpr int W = 2 * R + 1;
+    const size_t N = (size_t)nx * (size_t)ny * (size_t)nz;
+    const size_t rbase = (size_t)blockIdx.x * (size_t)nx;
+    const int x0 = (int)blockIdx.y * kTxChunk;
+    const int lo = max(0, x0 - R), hi = min(nx, x0 + kTxChunk + R);
+    for (int p = (int)threadIdx.x; p < hi - lo; p += 256) {
+#pragma unroll
+        for (int f = 0; f < 6; ++f) s[f][p] = Hb[(size_t)f * N + rbase + (size_t)(lo + p)];
+    }
+    __syncthreads();
+    const int x = x0 + (int)threadIdx.x;
+    if (x >= nx) return;
+    float acc[6] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+    if (x - 2 * R >= 0 && x + 2 * R <= nx - 1) {
+        const int lx = x - lo;
+#pragma unroll
+        for (int m = R; m >= -R; --m) {
+            const int am = m < 0 ? -m : m;
+            const float b0 = t.G[am], b1 = m > 0 ? t.D1[am] : (m < 0 ? -t.D1[am] : 0.f), b2 = t.D2[am];
+            const int li = lx - m;
+            acc[0] = fmaf(b2, s[0][li], acc[0]);
+            acc[1] = fmaf(b0, s[1][li], acc[1]);
+            acc[2] = fmaf(b0, s[2][li], acc[2]);
+            acc[3] = fmaf(b1, s[3][li], acc[3]);
+            acc[4] = fmaf(b1, s[4][li], acc[4]);
+            acc[5] = fmaf(b0, s[5][li], acc[5]);
+        }
+    } else {
+        const int i0 = max(0, x - R), i1 = min(nx - 1, x + R);
+        for (int i = i0; i <= i1; ++i) {
+            const int d = x - i + R;
+            const float b0 = B[(size_t)d * nx + i], b1 = B[(size_t)(W + d) * nx + i];
+            const float b2 = B[(size_t)(2 * W + d) * nx + i];
+            const int li = i - lo;
+            acc[0] = fmaf(b2, s[0][li], acc[0]);
+            acc[1] = fmaf(b0, s[1][li], acc[1]);
+            acc[2] = fmaf(b0, s[2][li], acc[2]);
+            acc[3] = fmaf(b1, s[3][li], acc[3]);
+            acc[4] = fmaf(b1, s[4][li], acc[4]);
+            acc[5] = fmaf(b0, s[5][li], acc[5]);
+        }
+    }
+    const size_t o = rbase + (size_t)x;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) X[(size_t)k * N + o] = acc[k];
+}
+
+// the fixed-radius x transpose for radii 2..10, else the generic one
+template <int R>
+static void launch_tx_lds(const float *Hb, float *X, const float *B, const AxisTaps &t, const dvr_grid &g,
+                          unsigned xchunks, hipStream_t st)
+{
+    if constexpr (R > 10) {
+        hipLaunchKernelGGL(k_tx_lds, dim3((unsigned)g.ny * (unsigned)g.nz, xchunks), dim3(256), 0, st, Hb, X, B, t,
+                           g.nx, g.ny, g.nz);
+    } else {
+        if (t.R != R) return launch_tx_lds<R + 1>(Hb, X, B, t, g, xchunks, st);
+        hipLaunchKernelGGL(k_tx_lds_r<R>, dim3((unsigned)g.ny * (unsigned)g.nz, xchunks), dim3(256), 0, st, Hb, X, B,
+                           t, g.nx, g.ny, g.nz);
+    }
+}
+
 // y and z: each lane walks a run of kTRun consecutive outputs along the axis at one position of the
 // other two (k_ty_run: blockIdx.y = run, blockIdx.z = z; k_tz_run: blockIdx.y = run), so every input
 // row along the axis is loaded once per run rather than once per output it reaches (2R + 1 times:
@@ -628,8 +700,7 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
         float *X = Hs, *Y = w.zws;  // this scale's H is no longer needed
         const unsigned xchunks = (unsigned)((g.nx + kTxChunk - 1) / kTxChunk);
         if (xchunks <= 65535u)
-            hipLaunchKernelGGL(k_tx_lds, dim3((unsigned)g.ny * (unsigned)g.nz, xchunks), dim3(256), 0, st, w.Hb, X,
-                               bt[s][0], p.taps[s].ax[0], g.nx, g.ny, g.nz);
+            launch_tx_lds<2>(w.Hb, X, bt[s][0], p.taps[s].ax[0], g, xchunks, st);
         else
             hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
         hipLaunchKernelGGL(k_ty_run<kTyRun>, tygrid, dim3(64), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
