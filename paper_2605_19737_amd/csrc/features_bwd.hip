@@ -529,6 +529,115 @@ __global__ __launch_bounds__(64) void k_tz_run(const float *__restrict__ Y, floa
         if (q < nq) dvol[(size_t)(zb + q) * plane + e] += acc[q];
 }
 
+// Fixed-radius forms of k_ty_run and k_tz_run (R = 2..10): the walk over the K + 2R input rows of
+// a run is unrolled, row j of the run (i = start - R + j) reaches outputs q with j - 2R <= q <= j at
+// band offset d = q - j + 2R, both known at compile time, so only the axis ends and the run's
+// ragged tail are tested at run time.  Same rows, products and order: the same bits.
+template <int K, int R>
+__global__ __launch_bounds__(64) void k_ty_run_r(const float *__restrict__ X, float *__restrict__ Y,
+                                                 const float *__restrict__ B, int nx, int ny, int nz)
+{
+    const int x = (int)(blockIdx.x * 64u + threadIdx.x);
+    if (x >= nx) return;
+    const int yb = (int)blockIdx.y * K, z = (int)blockIdx.z;
+    const int nq = min(K, ny - yb);
+    const size_t plane = (size_t)nx * (size_t)ny, N = plane * (size_t)nz;
+    const size_t col = (size_t)z * plane + (size_t)x;
+    constexpr int W = 2 * R + 1;
+    float y0[K], y1[K], y2[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) y0[q] = y1[q] = y2[q] = 0.f;
+#pragma unroll
+    for (int j = 0; j < K + 2 * R; ++j) {
+        const int i = yb - R + j;
+        if (i < 0 || i > ny - 1) continue;
+        const size_t sidx = col + (size_t)i * nx;
+        const float x0 = X[sidx], x1 = X[N + sidx], x2 = X[2 * N + sidx];
+        const float x3 = X[3 * N + sidx], x4 = X[4 * N + sidx], x5 = X[5 * N + sidx];
+#pragma unroll
+        for (int q = (j - 2 * R > 0 ? j - 2 * R : 0); q <= (j < K - 1 ? j : K - 1); ++q) {
+            if (q >= nq) break;
+            const int d = q - j + 2 * R;
+            const float b0 = B[(size_t)d * ny + i], b1 = B[(size_t)(W + d) * ny + i];
+            const float b2 = B[(size_t)(2 * W + d) * ny + i];
+            y0[q] = fmaf(b0, x0, y0[q]);
+            y0[q] = fmaf(b2, x1, y0[q]);
+            y0[q] = fmaf(b1, x3, y0[q]);
+            y1[q] = fmaf(b0, x4, y1[q]);
+            y1[q] = fmaf(b1, x5, y1[q]);
+            y2[q] = fmaf(b0, x2, y2[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q) {
+        if (q < nq) {
+            const size_t o = col + (size_t)(yb + q) * nx;
+            Y[o] = y0[q];
+            Y[N + o] = y1[q];
+            Y[2 * N + o] = y2[q];
+        }
+    }
+}
+
+template <int K, int R>
+__global__ __launch_bounds__(64) void k_tz_run_r(const float *__restrict__ Y, float *__restrict__ dvol,
+                                                 const float *__restrict__ B, int nx, int ny, int nz)
+{
+    const size_t plane = (size_t)nx * (size_t)ny;
+    const size_t e = (size_t)blockIdx.x * 64u + threadIdx.x;
+    if (e >= plane) return;
+    const int zb = (int)blockIdx.y * K;
+    const int nq = min(K, nz - zb);
+    const size_t N = plane * (size_t)nz;
+    constexpr int W = 2 * R + 1;
+    float acc[K];
+#pragma unroll
+    for (int q = 0; q < K; ++q) acc[q] = 0.f;
+#pragma unroll
+    for (int j = 0; j < K + 2 * R; ++j) {
+        const int i = zb - R + j;
+        if (i < 0 || i > nz - 1) continue;
+        const size_t sidx = (size_t)i * plane + e;
+        const float v0 = Y[sidx], v1 = Y[N + sidx], v2 = Y[2 * N + sidx];
+#pragma unroll
+        for (int q = (j - 2 * R > 0 ? j - 2 * R : 0); q <= (j < K - 1 ? j : K - 1); ++q) {
+            if (q >= nq) break;
+            const int d = q - j + 2 * R;
+            const float b0 = B[(size_t)d * nz + i], b1 = B[(size_t)(W + d) * nz + i];
+            const float b2 = B[(size_t)(2 * W + d) * nz + i];
+            acc[q] = fmaf(b0, v0, acc[q]);
+            acc[q] = fmaf(b1, v1, acc[q]);
+            acc[q] = fmaf(b2, v2, acc[q]);
+        }
+    }
+#pragma unroll
+    for (int q = 0; q < K; ++q)
+        if (q < nq) dvol[(size_t)(zb + q) * plane + e] += acc[q];
+}
+
+// the fixed-radius y and z transposes for radii 2..10, else the generic ones
+template <int R>
+static void launch_ty(const float *X, float *Y, const float *B, int Ry, const dvr_grid &g, dim3 grid, hipStream_t st)
+{
+    if constexpr (R > 10) {
+        hipLaunchKernelGGL(k_ty_run<kTyRun>, grid, dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz, Ry);
+    } else {
+        if (Ry != R) return launch_ty<R + 1>(X, Y, B, Ry, g, grid, st);
+        hipLaunchKernelGGL((k_ty_run_r<kTyRun, R>), grid, dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz);
+    }
+}
+
+template <int R>
+static void launch_tz(const float *Y, float *dvol, const float *B, int Rz, const dvr_grid &g, dim3 grid, hipStream_t st)
+{
+    if constexpr (R > 10) {
+        hipLaunchKernelGGL(k_tz_run<kTzRun>, grid, dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz, Rz);
+    } else {
+        if (Rz != R) return launch_tz<R + 1>(Y, dvol, B, Rz, g, grid, st);
+        hipLaunchKernelGGL((k_tz_run_r<kTzRun, R>), grid, dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz);
+    }
+}
+
 // dL/d|g|_max to the arg-max voxel's gradient: d|g|/dg = g / |g|
 template <int DT>
 __global__ void k_fb_gmax(const void *__restrict__ vol, const unsigned long long *__restrict__ key,
@@ -703,8 +812,8 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
             launch_tx_lds<2>(w.Hb, X, bt[s][0], p.taps[s].ax[0], g, xchunks, st);
         else
             hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
-        hipLaunchKernelGGL(k_ty_run<kTyRun>, tygrid, dim3(64), 0, st, X, Y, bt[s][1], g.nx, g.ny, g.nz, p.taps[s].ax[1].R);
-        hipLaunchKernelGGL(k_tz_run<kTzRun>, tzgrid, dim3(64), 0, st, Y, dvol, bt[s][2], g.nx, g.ny, g.nz, p.taps[s].ax[2].R);
+        launch_ty<2>(X, Y, bt[s][1], p.taps[s].ax[1].R, g, tygrid, st);
+        launch_tz<2>(Y, dvol, bt[s][2], p.taps[s].ax[2].R, g, tzgrid, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (vol_dt == DVR_F32)
