@@ -14,8 +14,9 @@
 //      first scale, and at the voxel's winning scale dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T from
 //      a Jacobi eigen-decomposition; at the first scale it also writes dL/dg + dL/dk dk/dg and
 //      the arg-max key of |g|;
-//   2. k_tx, k_ty_run, k_tz_run apply the transposed x, y and z operators (the forward's z-then-y-then-x
-//      order reversed: six fields after x, three after y, one accumulated into dL/dI after z).
+//   2. the x, y and z transposes apply the transposed operators (the forward's z-then-y-then-x order
+//      reversed: six fields after x, three after y, one accumulated into dL/dI after z): for radii
+//      2..10 k_tx_lds_r, k_ty_run_r, k_tz_run_r, else k_tx_lds (k_tx), k_ty_run, k_tz_run.
 // Last, dL/d|g|_max goes to the arg-max voxel's gradient (k_fb_gmax) and the transposed central
 // difference of the gradient is added (k_fb_gradT).
 //
