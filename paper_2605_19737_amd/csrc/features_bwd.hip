@@ -616,26 +616,39 @@ __global__ __launch_bounds__(64) void k_tz_run_r(const float *__restrict__ Y, fl
         if (q < nq) dvol[(size_t)(zb + q) * plane + e] += acc[q];
 }
 
-// the fixed-radius y and z transposes for radii 2..10, else the generic ones
+// the fixed-radius y and z transposes for radii 2..10 (runs of kTyRunR, kTzRunR), else the generic
+// ones (runs of kTyRun, kTzRun)
+constexpr int kTyRunR = 8, kTzRunR = 8;
+static dim3 ty_grid(const dvr_grid &g, int K)
+{
+    return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + K - 1) / K), (unsigned)g.nz);
+}
+static dim3 tz_grid(const dvr_grid &g, int K)
+{
+    const size_t plane = (size_t)g.nx * (size_t)g.ny;
+    return dim3((unsigned)((plane + 63) / 64), (unsigned)((g.nz + K - 1) / K));
+}
+
 template <int R>
-static void launch_ty(const float *X, float *Y, const float *B, int Ry, const dvr_grid &g, dim3 grid, hipStream_t st)
+static void launch_ty(const float *X, float *Y, const float *B, int Ry, const dvr_grid &g, hipStream_t st)
 {
     if constexpr (R > 10) {
-        hipLaunchKernelGGL(k_ty_run<kTyRun>, grid, dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz, Ry);
+        hipLaunchKernelGGL(k_ty_run<kTyRun>, ty_grid(g, kTyRun), dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz, Ry);
     } else {
-        if (Ry != R) return launch_ty<R + 1>(X, Y, B, Ry, g, grid, st);
-        hipLaunchKernelGGL((k_ty_run_r<kTyRun, R>), grid, dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz);
+        if (Ry != R) return launch_ty<R + 1>(X, Y, B, Ry, g, st);
+        hipLaunchKernelGGL((k_ty_run_r<kTyRunR, R>), ty_grid(g, kTyRunR), dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz);
     }
 }
 
 template <int R>
-static void launch_tz(const float *Y, float *dvol, const float *B, int Rz, const dvr_grid &g, dim3 grid, hipStream_t st)
+static void launch_tz(const float *Y, float *dvol, const float *B, int Rz, const dvr_grid &g, hipStream_t st)
 {
     if constexpr (R > 10) {
-        hipLaunchKernelGGL(k_tz_run<kTzRun>, grid, dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz, Rz);
+        hipLaunchKernelGGL(k_tz_run<kTzRun>, tz_grid(g, kTzRun), dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz, Rz);
     } else {
-        if (Rz != R) return launch_tz<R + 1>(Y, dvol, B, Rz, g, grid, st);
-        hipLaunchKernelGGL((k_tz_run_r<kTzRun, R>), grid, dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz);
+        if (Rz != R) return launch_tz<R + 1>(Y, dvol, B, Rz, g, st);
+        hipLaunchKernelGGL((k_tz_run_r<kTzRunR, R>), tz_grid(g, kTzRunR), dim3(64), 0, st, Y, dvol, B, g.nx, g.ny,
+                           g.nz);
     }
 }
 
@@ -764,8 +777,6 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
     const uint32_t N = plane * (uint32_t)g.nz;
     const dim3 pgrid((plane + 255) / 256, g.nz);
-    const dim3 tygrid((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + kTyRun - 1) / kTyRun), (unsigned)g.nz);
-    const dim3 tzgrid((unsigned)((plane + 63) / 64), (unsigned)((g.nz + kTzRun - 1) / kTzRun));
     const dim3 vgrid((N + 255) / 256);
     hipError_t e;
     // band tables of every scale and axis (one launch per scale)
@@ -813,8 +824,8 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
             launch_tx_lds<2>(w.Hb, X, bt[s][0], p.taps[s].ax[0], g, xchunks, st);
         else
             hipLaunchKernelGGL(k_tx, pgrid, dim3(256), 0, st, w.Hb, X, bt[s][0], g.nx, g.ny, g.nz, p.taps[s].ax[0].R);
-        launch_ty<2>(X, Y, bt[s][1], p.taps[s].ax[1].R, g, tygrid, st);
-        launch_tz<2>(Y, dvol, bt[s][2], p.taps[s].ax[2].R, g, tzgrid, st);
+        launch_ty<2>(X, Y, bt[s][1], p.taps[s].ax[1].R, g, st);
+        launch_tz<2>(Y, dvol, bt[s][2], p.taps[s].ax[2].R, g, st);
         if ((e = hipGetLastError()) != hipSuccess) return e;
     }
     if (vol_dt == DVR_F32)
