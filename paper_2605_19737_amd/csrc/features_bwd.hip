@@ -275,7 +275,17 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
             const unsigned long long w = __shfl_xor(kv, o, 64);
             kv = w > kv ? w : kv;
         }
-        if ((threadIdx.x & 63) == 0 && kv != 0ull) atomicMax(key, kv);
+        // one key per workgroup, and an atomic only when it beats the current maximum: atomics on
+        // one address serialize in the L2, and one per wave cost about a millisecond on the head
+        // (a stale read of the key is never above the true maximum, so skipping stays exact)
+        __shared__ unsigned long long wkey[4];
+        if ((threadIdx.x & 63) == 0) wkey[threadIdx.x >> 6] = kv;
+        __syncthreads();
+        if (threadIdx.x == 0) {
+#pragma unroll
+            for (int k = 1; k < 4; ++k) kv = wkey[k] > kv ? wkey[k] : kv;
+            if (kv != 0ull && kv > __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(key, kv);
+        }
     }
 }
 
