@@ -165,6 +165,18 @@ dvr_status dvr_normalize_workspace(int64_t n, size_t *bytes);
 dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t out_dtype, int64_t n,
                          void *ws, size_t ws_bytes, hipStream_t stream);
 
+/* dvr_normalize without a caller workspace and without any allocation, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * it).  Same arguments, results and errors as dvr_normalize; the two reduction words live in a
+ * 256-byte static device array that the library holds on each GPU it runs on until the process
+ * ends (cleared by a fill kernel at the start of every call).  Every call on one GPU shares that
+ * array: calls that overlap on one GPU (different streams, or host threads) race and may give
+ * wrong results; calls ordered on one stream do not.  Returns DVR_E_WORKSPACE if the reduction
+ * would need more than the array holds (it needs 8 bytes for any n), DVR_E_DEVICE if the array's
+ * address cannot be looked up on the current device. */
+dvr_status dvr_normalize_noalloc(const void *raw, int32_t raw_dtype, void *out, int32_t out_dtype, int64_t n,
+                                 hipStream_t stream);
+
 /* Feature pass (Sec. 2.3 Eq. 2-3; Sec. 1 multi-scale Hessian and vesselness).
  *   gradient  g_a = (I[a+1] - I[a-1]) / (2 h_a), indices clamped to the grid (Eq. 2);
  *   gmax      max |g|_2 over all voxels, written to out->gmax;

@@ -110,6 +110,7 @@ def load():
     L.dvr_last_error.restype = C.c_char_p
     L.dvr_normalize_workspace.argtypes = [i64, P(sz)]
     L.dvr_normalize.argtypes = [vp, i32, vp, i32, i64, vp, sz, vp]
+    L.dvr_normalize_noalloc.argtypes = [vp, i32, vp, i32, i64, vp]
     L.dvr_features_workspace.argtypes = [P(Grid), P(FeatureParams), P(sz)]
     L.dvr_bricks_count.argtypes = [P(Grid), P(i64)]
     L.dvr_histogram.argtypes = [vp, i32, i64, C.c_float, vp, vp, vp]
@@ -132,7 +133,7 @@ def load():
     L.dvr_batch_check.argtypes = [vp, vp]
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
-    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_denoise_workspace", "dvr_denoise", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
+    for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_normalize_noalloc", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_denoise_workspace", "dvr_denoise", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
                  "dvr_render", "dvr_render_backward", "dvr_render_backward_features", "dvr_features_backward_workspace",
                  "dvr_features_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):

@@ -179,6 +179,30 @@ dvr_status dvr_normalize(const void *raw, int32_t raw_dtype, void *out, int32_t 
     return e == hipSuccess ? DVR_OK : dev_fail(e, "normalize launch");
 }
 
+dvr_status dvr_normalize_noalloc(const void *raw, int32_t raw_dtype, void *out, int32_t out_dtype, int64_t n,
+                                 hipStream_t stream)
+{
+    if (!raw || !out) return fail(DVR_E_NULL, "raw and out must be non-NULL");
+    if (!aligned16(raw) || !aligned16(out)) return fail(DVR_E_ALIGN, "raw and out must be 16-byte aligned");
+    if (n <= 0) return fail(DVR_E_INVALID_ARG, "n must be > 0");
+    if (raw_dtype != DVR_U16 && raw_dtype != DVR_F32 && raw_dtype != DVR_F16)
+        return fail(DVR_E_UNSUPPORTED, "raw dtype must be U16, F32 or F16");
+    if (out_dtype != DVR_F16 && out_dtype != DVR_F32) return fail(DVR_E_UNSUPPORTED, "out dtype must be F16 or F32");
+    // the reduction needs the two words of dvr_normalize's workspace whatever n is; refuse anything
+    // that would need more than the static scratch holds
+    size_t need = 0;
+    dvr_status s = dvr_normalize_workspace(n, &need);
+    if (s) return s;
+    if (need > dvr::normalize_scratch_bytes())
+        return fail(DVR_E_WORKSPACE, "normalize needs %zu bytes of scratch; the static scratch holds %zu", need,
+                    dvr::normalize_scratch_bytes());
+    void *scratch = nullptr;
+    hipError_t e = dvr::normalize_scratch(&scratch);
+    if (e != hipSuccess) return dev_fail(e, "static scratch lookup");
+    e = dvr::launch_normalize(raw, raw_dtype, out, out_dtype, n, (uint32_t *)scratch, stream);
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "normalize launch");
+}
+
 dvr_status dvr_denoise_workspace(const dvr_grid *grid, int32_t mode, size_t *bytes)
 {
     dvr_status s = check_grid(grid);

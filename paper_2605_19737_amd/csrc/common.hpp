@@ -125,6 +125,9 @@ hipError_t launch_quads(const void *src, void *dst, const dvr_grid &g, int dtype
 
 hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, int64_t n, uint32_t *ws,
                             hipStream_t st);
+// The allocation-free normalize's scratch (normalize.hip): its size, and this device's address of it.
+size_t normalize_scratch_bytes();
+hipError_t normalize_scratch(void **ptr);
 
 hipError_t launch_histogram(const void *vol, int dt, int64_t n, float floor_, uint32_t *hist, uint32_t *used,
                             hipStream_t st);

@@ -3,6 +3,8 @@
 // reduction, and one atomic per workgroup on an order-preserving unsigned encoding, skipped when it
 // cannot change the global value (device-scope atomics on one address serialize).  Pass 2 scales and
 // stores 16 input bytes per lane and step (F16 rounded to nearest even, or F32).
+#include <mutex>
+
 #include "common.hpp"
 
 namespace dvr {
@@ -168,6 +170,41 @@ hipError_t launch_normalize(const void *raw, int raw_dt, void *out, int out_dt, 
     if (raw_dt == DVR_U16) return launch_norm_t<DVR_U16>(raw, out, out_dt, n, ws, st);
     if (raw_dt == DVR_F32) return launch_norm_t<DVR_F32>(raw, out, out_dt, n, ws, st);
     return launch_norm_t<DVR_F16>(raw, out, out_dt, n, ws, st);
+}
+
+// ------------------------------------------------------------------------------------------------
+// Library-owned scratch of the allocation-free entry point (dvr_normalize_noalloc): the two
+// reduction words, in a file-scope device array that every GPU the library runs on holds until the
+// process ends.  Host code never passes the array's name to a kernel (on the host it is only a
+// stand-in for the symbol): its device address is looked up once per device with
+// hipGetSymbolAddress, with that device current, and kept here.
+constexpr size_t kNormScratchBytes = 256;
+static __device__ __align__(256) uint32_t scratch[kNormScratchBytes / sizeof(uint32_t)];
+
+constexpr int kMaxDevices = 64;
+static std::mutex g_scratch_mu;
+static void *g_scratch_ptr[kMaxDevices];
+
+size_t normalize_scratch_bytes() { return kNormScratchBytes; }
+
+// Device address of this device's scratch (the current device); hipSuccess and *ptr set, or the
+// HIP error of the lookup.
+hipError_t normalize_scratch(void **ptr)
+{
+    int dev = -1;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return e;
+    if (dev < 0 || dev >= kMaxDevices) return hipErrorInvalidDevice;
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (!g_scratch_ptr[dev]) {
+        void *p = nullptr;
+        e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+        if (e != hipSuccess) return e;
+        if (!p) return hipErrorInvalidSymbol;
+        g_scratch_ptr[dev] = p;
+    }
+    *ptr = g_scratch_ptr[dev];
+    return hipSuccess;
 }
 
 }  // namespace dvr
