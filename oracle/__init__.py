@@ -59,7 +59,7 @@ def lib():
         L.oracle_render.argtypes = [dp, dp, dp, dp, i, i, i, d, d, d, d, i, dp, dp, dp, dp, i, ip, i64,
                                     dp, dp, ip, i64p]
         L.oracle_render_vjp.argtypes = [dp, dp, dp, dp, i, i, i, d, d, d, d, i, dp, dp, dp, dp, i, ip, i64,
-                                        dp, dp, dp, dp, dp, dp, dp, d, C.POINTER(C.c_uint8)]
+                                        dp, dp, dp, dp, dp, dp, dp, d, i, C.POINTER(C.c_uint8)]
         _lib = L
     return _lib
 
@@ -209,11 +209,13 @@ def render(vol, feats, gmax, spacing, knots, rgba, params, cams, pix=None):
 
 
 def render_vjp(vol, feats, gmax, spacing, knots, rgba, params, cams, dout, pix=None, want_dI=True,
-               want_features=False, near_knot_eps=None):
+               want_features=False, near_knot_eps=None, near_knot_weighted=False):
     """dL/d(TF values) [K][4] and dL/dI [nz][ny][nx] for upstream dout (same layout as render).
     want_features: also dict(g [3][nz][ny][nx], kappa, V, gmax) of dL/d(feature values), returned
     as a third element.  near_knot_eps: also a bool [nz][ny][nx] mask of the corners of samples
-    whose intensity lies within that distance of a TF knot, returned last."""
+    whose intensity lies within that distance of a TF knot, returned last; near_knot_weighted:
+    within that distance times the corner's trilinear weight (the voxels whose change by
+    +-near_knot_eps moves some sample across a knot)."""
     camarr = pack_cams(cams)
     pix = all_pixels(cams) if pix is None else np.ascontiguousarray(pix, dtype=np.int32)
     d = _f64(dout).reshape(-1, 4)
@@ -229,7 +231,7 @@ def render_vjp(vol, feats, gmax, spacing, knots, rgba, params, cams, dout, pix=N
     rc = lib().oracle_render_vjp(*args, _p(camarr), len(camarr), _p(pix, C.c_int32), len(pix), _p(d),
                                  _p(dtf), _p(dI), _p(fg["g"]) if fg else None, _p(fg["kappa"]) if fg else None,
                                  _p(fg["V"]) if fg else None, C.byref(dgm) if fg else None,
-                                 float(near_knot_eps or 0.0), _p(nk, C.c_uint8))
+                                 float(near_knot_eps or 0.0), int(bool(near_knot_weighted)), _p(nk, C.c_uint8))
     assert rc == 0
     del keep
     out = [dtf, dI]

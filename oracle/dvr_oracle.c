@@ -511,14 +511,16 @@ int oracle_render(const double *I, const double *g, const double *kap, const dou
 /* w (|k| / (|k| + k0), derivative 0 at k = 0) and u (1 + lambda_v V).  All outputs overwritten.   */
 /* near_knot (nullable, [N] bytes, test support): set to 1 at the 8 corners of every sample whose  */
 /* intensity lies within knot_eps of a TF knot (the TF slope jumps there, so a lower-precision     */
-/* evaluation may take the neighbouring segment), 0 elsewhere.                                     */
+/* evaluation may take the neighbouring segment), 0 elsewhere.  knot_weighted != 0: set at corner  */
+/* c only if the sample lies within w_c knot_eps of a knot (w_c its trilinear weight): exactly the */
+/* voxels whose change by +-knot_eps can move some sample across a knot (a kink of the loss).      */
 int oracle_render_vjp(const double *I, const double *g, const double *kap, const double *ves,
                       int nx, int ny, int nz, double hx, double hy, double hz, double gmax,
                       int K, const double *knots, const double *rgba, const double *prm,
                       const double *cams, int ncam, const int32_t *pix, int64_t npix,
                       const double *dout, double *dL_dtf, double *dL_dI,
                       double *dL_dg, double *dL_dkap, double *dL_dves, double *dL_dgmax,
-                      double knot_eps, uint8_t *near_knot)
+                      double knot_eps, int knot_weighted, uint8_t *near_knot)
 {
     if (nx < 2 || ny < 2 || nz < 2 || K < 2) return -1;
     scene_t sc;
@@ -577,13 +579,17 @@ int oracle_render_vjp(const double *I, const double *g, const double *kap, const
                 if (near_knot) {
                     double I = 0.0;
                     for (int c8 = 0; c8 < 8; ++c8) I += s->cn.w[c8] * sc.I[s->cn.idx[c8]];
-                    int near = 0;
-                    for (int kk = 0; kk < K; ++kk) near |= fabs(I - knots[kk]) < knot_eps;
-                    if (near)
-                        for (int c8 = 0; c8 < 8; ++c8) {
+                    double dmin = INFINITY;
+                    for (int kk = 0; kk < K; ++kk) dmin = fmin(dmin, fabs(I - knots[kk]));
+                    for (int c8 = 0; c8 < 8; ++c8) {
+                        /* weighted: a small margin covers the rounding of I (FP64) */
+                        const int near = knot_weighted ? (dmin <= knot_eps * s->cn.w[c8] * (1.0 + 1e-9) + 1e-14)
+                                                       : (dmin < knot_eps);
+                        if (near) {
 #pragma omp atomic write
                             near_knot[s->cn.idx[c8]] = 1;
                         }
+                    }
                 }
                 if (want_feat) {
                     /* x = tau M dk */

@@ -1,6 +1,8 @@
 """Batched persistent launch (dvr_batch_*): the features of several uneven, anisotropic volumes and
-4 views of each, in one persistent kernel recorded in a HIP graph.  Every volume's features and
-every view's image and ray state equal the standalone dvr_features / dvr_render results bitwise
+4 views of each, in one persistent kernel recorded in a HIP graph.  On eight volumes of the
+64-volume set at 512^2 the launch is compared with the FP64 oracle directly (features of every
+volume, one whole view of each and sampled pixels of the other three).  Every volume's features and
+every view's image and ray state also equal the standalone dvr_features / dvr_render results bitwise
 (the same arithmetic per voxel and per ray), for every tile shape the autotuner can choose; a TF
 edited in place is picked up by the next replay; the dependency-wait timeout path reports
 DVR_E_TIMEOUT while the kernel still exits normally."""
@@ -13,7 +15,8 @@ import torch
 import paper_2605_19737_amd as dvr
 import phantoms
 from paper_2605_19737_amd import _abi as abi
-from tests.gpu_common import to_dev
+import oracle  # noqa: E402  (the checker)
+from tests.gpu_common import compare_features, compare_images, f32, feats_np, oracle_params, sp32, to_dev
 
 pytestmark = pytest.mark.gpu
 
@@ -56,6 +59,54 @@ def _assert_equal(feats, views, ref_f, ref_v):
         assert torch.equal(a.gmax, b.gmax)
     for (i, cam, img, T, k), (rimg, rT, rk) in zip(views, ref_v):
         assert torch.equal(img, rimg[0]) and torch.equal(T, rT[0]) and torch.equal(k, rk[0])
+
+
+def test_batch_against_oracle_c4_subset():
+    """Volumes 0-7 of the 64-volume batched set (uneven shapes from 100x219x123 to 252x124x71, 2.2-6.1 M
+    voxels, in-plane 0.54-1.10 mm, slices 3.6-5.0 mm), each with its 4 orthographic 512^2 views, in one graph launch with the split
+    layout the benchmark's batched leg uses.  Every volume's g, kappa, V and |g|_max against the oracle
+    (1e-5 / 1e-6); view 0 of every volume whole and 3000 sampled pixels of each other view (RGBA and
+    T_last within 1e-5, k_last equal)."""
+    nvol = 8
+    ws = [phantoms.c4_volume(b, 512, 512) for b in range(nvol)]
+    vols = [to_dev(w.vol) for w in ws]
+    sps = [w.spacing for w in ws]
+    lay = abi.DVR_SPLIT
+    feats = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
+    views = []
+    for i, w in enumerate(ws):
+        for cam in w.cams:
+            views.append((i, cam, torch.empty((512, 512, 4), dtype=torch.float32, device="cuda"),
+                          torch.empty((512, 512), dtype=torch.float32, device="cuda"),
+                          torch.empty((512, 512), dtype=torch.int32, device="cuda")))
+    knots, rgba = to_dev(ws[0].tf_knots), to_dev(ws[0].tf_rgba)
+    print(f"[batch-oracle] {nvol} volumes {[tuple(v.shape) for v in vols]}, {len(views)} views 512^2", flush=True)
+    b = dvr.Batch(vols, sps, feats, views, ws[0].sigmas, knots, rgba, ws[0].params, c=ws[0].c)
+    b.launch()
+    b.check()
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(44)
+    for i, w in enumerate(ws):
+        sp = sp32(w.spacing)
+        v64 = vols[i].cpu().numpy().astype(np.float64)
+        of = oracle.features(v64, sp, [f32(s) for s in w.sigmas], c=f32(w.c), want_lam=True)
+        compare_features(feats_np(feats[i]), of, f"batched volume {i} {tuple(v64.shape)}")
+        mine = [vw for vw in views if vw[0] == i]
+        prm = oracle_params(w.params)
+        et = f32(w.params["et_alpha"])
+        # view 0 whole
+        _, cam, img, T, k = mine[0]
+        ref = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, [cam])
+        compare_images(img[None], T[None], k[None], ref, et, f"batched volume {i} view 0 (whole)")
+        # views 1-3 on sampled pixels
+        M = 3000
+        pix = np.stack([rng.integers(0, 3, M), rng.integers(0, 512, M), rng.integers(0, 512, M)], 1).astype(np.int32)
+        cams = [vw[1] for vw in mine[1:]]
+        ref = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, cams, pix=pix)
+        compare_images(torch.stack([vw[2] for vw in mine[1:]]), torch.stack([vw[3] for vw in mine[1:]]),
+                       torch.stack([vw[4] for vw in mine[1:]]), ref, et, f"batched volume {i} views 1-3 (sampled)",
+                       pix=pix)
+    b.close()
 
 
 @pytest.mark.parametrize("tune", [None, dict(wg_per_cu=2, xy_tile=1, xy_zrun=3, z_chunk=5, ray_tile=1),
