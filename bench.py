@@ -502,7 +502,7 @@ def leg_c5(dev, stream, dvr, torch, np, log):
     for it in range(4):
         e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
         e0.record(stream)
-        dvr.features(v32, w.spacing, w.sigmas, c=w.c, eig_gap=1e-2, layout=abi.DVR_PLANAR, out=f32, ws=ws32)
+        dvr.features(v32, w.spacing, w.sigmas, c=w.c, eig_gap=1e-3, layout=abi.DVR_PLANAR, out=f32, ws=ws32)
         e1.record(stream)
         torch.cuda.synchronize()
         if it > 0:

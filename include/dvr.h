@@ -254,7 +254,8 @@ dvr_status dvr_tissue_tf(const dvr_peaks *peaks, const dvr_tissue_tf_params *par
  * trilinearly interpolates I, g, kappa, V; the TF (piecewise linear, clamped) gives colour c and
  * extinction tau; sigma = tau * m * w * u with m = (1 - lambda_g) + lambda_g min(|g|/gmax, 1),
  * w = (1 - lambda_k) + lambda_k |k| / (|k| + kappa0), u = 1 + lambda_v V; alpha = 1 - exp(-sigma
- * delta_k); C += T alpha c, T *= 1 - alpha (Eq. 5-6 in transmittance form), A = 1 - T.
+ * delta_k); C += T alpha c, A += T alpha, T *= 1 - alpha (Eq. 5-6; A equals 1 - T in exact
+ * arithmetic and is summed so that faint rays keep their relative accuracy).
  * vol: device [nz][ny][nx] of vol_dtype, 16-byte aligned, the feature dtype: the intensity that is
  * sampled for PLANAR and SPLIT features; ignored (may be NULL) for INTERLEAVED and QUAD, whose
  * records or iquad carry it (the same holds for the adjoints below).

@@ -145,14 +145,14 @@ def alloc_features(shape_zyx, spacing, dtype=torch.float32, layout=abi.DVR_PLANA
     return Features(grad, kappa, ves, gmax, layout, tuple(shape_zyx), tuple(spacing), bt, iq)
 
 
-def features_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2):
+def features_workspace_bytes(shape_zyx, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-3):
     n = C.c_size_t()
     abi.check(lib().dvr_features_workspace(C.byref(grid_struct(shape_zyx, spacing)),
                                            C.byref(_fparams(sigmas, alpha, beta, c, eig_gap)), C.byref(n)))
     return n.value
 
 
-def features(vol, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2, dtype=None, layout=abi.DVR_PLANAR,
+def features(vol, spacing, sigmas, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-3, dtype=None, layout=abi.DVR_PLANAR,
              out=None, ws=None):
     """Feature pass (dvr_features): gradient, |grad I|_max, k and vesselness of vol [nz][ny][nx]."""
     _require_cuda(vol)
@@ -365,7 +365,7 @@ class Batch:
     The TF tensors are read at every launch: edit them in place to change the transfer function."""
 
     def __init__(self, vols, spacings, feats, views, sigmas, knots, rgba, params, alpha=0.5, beta=0.5, c=0.1,
-                 eig_gap=1e-2, tune=None):
+                 eig_gap=1e-3, tune=None):
         self._keep = (list(vols), list(feats), list(views), knots, rgba)
         self.desc = self._desc(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha, beta, c, eig_gap, tune)
         self.plan = C.c_void_p()
@@ -412,7 +412,7 @@ class Batch:
             pass
 
     @staticmethod
-    def autotune(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-2,
+    def autotune(vols, spacings, feats, views, sigmas, knots, rgba, params, alpha=0.5, beta=0.5, c=0.1, eig_gap=1e-3,
                  cache_path=None):
         """dvr_batch_autotune: returns the fastest tune as a dict (and caches it in cache_path)."""
         tmp = Batch.__new__(Batch)

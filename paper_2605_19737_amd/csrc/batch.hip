@@ -311,7 +311,7 @@ __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
             const RayOut o = march_fwd<LAYOUT, DT, KMAX>(f, g, sh, kx, A.rp, invg, r);
             if (valid) {
                 const size_t pix = (size_t)pj * Vw.W + pi;
-                reinterpret_cast<float4 *>(Vw.rgba)[pix] = make_float4(o.C0, o.C1, o.C2, 1.f - o.T);
+                reinterpret_cast<float4 *>(Vw.rgba)[pix] = make_float4(o.C0, o.C1, o.C2, o.A);
                 if (Vw.T_last) {
                     Vw.T_last[pix] = o.Tprev;
                     if (Vw.k_last) Vw.k_last[pix] = o.last;
@@ -465,7 +465,9 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
             ScaleTaps &t = taps[(size_t)v * ns + sc];
             for (int a = 0; a < 3; ++a) axis_taps((double)fp.sigma_mm[sc] / h[a], h[a], t.ax[a]);
             t.sigma2 = (float)((double)fp.sigma_mm[sc] * fp.sigma_mm[sc]);
-            lds_floats = std::max(lds_floats, (size_t)(3 * (TY + 2 * t.ax[1].R) + 6 * TY) * (size_t)(TX + 2 * t.ax[0].R));
+            const size_t st = (size_t)3 * (TY + 2 * t.ax[1].R) * (TX + 2 * t.ax[0].R),
+                         cw = (size_t)Compact<2>::kFloats;
+            lds_floats = std::max(lds_floats, std::max(st, cw) + (size_t)6 * TY * (TX + 2 * t.ax[0].R));
         }
         ws_total += (size_t)ns * 12u * (size_t)nvox(&bv.grid);
         if (layout == DVR_QUAD) ws_total += ((size_t)4u * (size_t)nvox(&bv.grid) + 255u) & ~(size_t)255u;

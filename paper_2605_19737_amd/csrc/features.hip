@@ -94,14 +94,48 @@ __global__ __launch_bounds__(NT) void k_xypass(XYArgs a, ScaleTaps taps)
     }
 }
 
-// Fixed-radius variant (x and y stencil radius R, equal) for the layouts the workloads use.
+// Fixed-radius variant (x and y stencil radius R, equal) for the layouts the workloads use: one
+// workgroup per (x, y) tile and run of kZRun z slices, each slice's loads in flight while the previous
+// slice is computed.
+constexpr int kZRun = 1;
+
 template <int DT, int OUT_DT, int LAYOUT, int R>
 __global__ __launch_bounds__(NT) void k_xypass_r(XYArgs a, ScaleTaps taps)
 {
     using T = XYTileR<R, TX, TY>;
-    __shared__ float F[T::NST];
+    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY>;
+    __shared__ float F[T::NF];
     __shared__ float Fy[T::NFY];
-    float vmax = xy_tile_r<DT, OUT_DT, LAYOUT, R, TX, TY>(a, taps, blockIdx.x * TX, blockIdx.y * TY, blockIdx.z, F, Fy);
+    S s(a, taps, F, Fy, blockIdx.x * TX, blockIdx.y * TY);
+    float vmax = 0.f;
+    if constexpr (kZRun == 1) {
+        const int z = blockIdx.z;
+        s.load(z);
+        s.store();
+        __syncthreads();
+        vmax = s.compute(z, s.In, s.Vp);
+        if (a.fro_pass || a.first) {
+            vmax = wave_max(vmax);
+            if ((threadIdx.x & 63) == 0) atomic_max_pos(a.fro_pass ? a.fro : a.gmax, vmax);
+        }
+        return;
+    }
+    const int z0 = blockIdx.z * kZRun, z1 = min(z0 + kZRun, a.nz);
+    s.load(z0);
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();  // the previous slice's readers of F (its y filters, its compaction lists) are done
+        s.store();
+        float Ic[S::NV][7], Vc[S::NV];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i) {
+            Vc[i] = s.Vp[i];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) Ic[i][k] = s.In[i][k];
+        }
+        if (z + 1 < z1) s.load(z + 1);
+        __syncthreads();
+        vmax = fmaxf(vmax, s.compute(z, Ic, Vc));
+    }
     if (a.fro_pass || a.first) {
         vmax = wave_max(vmax);
         if ((threadIdx.x & 63) == 0) atomic_max_pos(a.fro_pass ? a.fro : a.gmax, vmax);
@@ -117,7 +151,7 @@ static hipError_t launch_xy_r(const XYArgs &a, const ScaleTaps &taps, hipStream_
         return hipErrorInvalidValue;
     } else {
         if (taps.ax[0].R != R) return launch_xy_r<DT, OUT_DT, LAYOUT, R + 1>(a, taps, st);
-        dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY, a.nz);
+        dim3 grid((a.nx + TX - 1) / TX, (a.ny + TY - 1) / TY, (a.nz + kZRun - 1) / kZRun);
         hipLaunchKernelGGL((k_xypass_r<DT, OUT_DT, LAYOUT, R>), grid, dim3(NT), 0, st, a, taps);
         return hipGetLastError();
     }

@@ -41,42 +41,163 @@ __device__ __forceinline__ void eig_trig(T a00, T a11, T a22, T a01, T a02, T a1
     lmid = (a00 + a11 + a22) - lmax - lmin;
 }
 
-// Eigenvalues in FP32; re-solved in FP64 when the smallest gap is below tau * max|lambda|
-// (the closed form loses accuracy as two roots merge).  Returned sorted by (|l|, l) ascending.
-__device__ __forceinline__ void eig_sorted(const float A[6], float tau, float &l1, float &l2, float &l3)
+// Eigenvalues of a symmetric 3x3 matrix in FP32 with an accuracy of a few ulps of max|lambda| at any
+// gap between them.  The closed form above takes cos(3 phi) from det(B) / p^3, whose rounding is
+// amplified by ~p / gap where two roots merge.  Here the characteristic cubic of the traceless
+// B = A - m I (m = tr A / 3) is solved through its two invariants J2 = tr(B^2) / 2, J3 = det B and
+// its discriminant Delta = prod_{i<j} (lambda_i - lambda_j)^2 = 4 J2^3 - 27 J3^2, which is
+// computed without that cancellation: Delta is the Gram determinant of the vectors I, B, B^2 under
+// the Frobenius product (a Vandermonde determinant squared), so by Cauchy-Binet it is the sum of
+// the squared 3x3 minors of [vec I; vec B; vec B^2] (off-diagonal coordinates weighted by sqrt 2):
+//   Delta = M0^2 + 2 sum_{i<j, k} (c_k (b_jj - b_ii) - b_k (c_jj - c_ii))^2 + 12 sum_{k<l} (b_k c_l - b_l c_k)^2
+// with C = B^2, M0 = c00 (b22 - b11) + c11 (b00 - b22) + c22 (b11 - b00), k, l over the
+// off-diagonal entries.  Then 3 theta = atan2(sqrt Delta, 3 sqrt(3) J3) in [0, pi] and the roots
+// are m + 2 p cos(theta + 2 pi j / 3), p = sqrt(J2 / 3).  B is first scaled by its largest entry
+// (Delta is of degree 6 in B: no underflow or overflow), and the angle functions are polynomials
+// on the ranges they are needed on (atan on [0, 1]; sin and cos on [0, pi/3]), least-squares fits
+// with errors of 6e-9, 4e-11 and 8e-10, below FP32 resolution.  Returned in ascending order.
+__device__ __forceinline__ float atan01(float t)
 {
-    float lo, mi, hi;
-    eig_trig<float>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
-    const float gap = fminf(hi - mi, mi - lo);
-    const float scl = fmaxf(fabsf(hi), fabsf(lo));
-    if (gap < tau * scl) {
-        double dlo, dmi, dhi;
-        eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], dlo, dmi, dhi);
-        lo = (float)dlo;
-        mi = (float)dmi;
-        hi = (float)dhi;
-    }
-    // order by magnitude, the negative one first on an exact tie
-    float a = lo, b = mi, c = hi, t;
-#define DVR_KEY_LESS(u, v) (fabsf(u) < fabsf(v) || (fabsf(u) == fabsf(v) && (u) < (v)))
-    if (DVR_KEY_LESS(b, a)) { t = a; a = b; b = t; }
-    if (DVR_KEY_LESS(c, b)) { t = b; b = c; c = t; }
-    if (DVR_KEY_LESS(b, a)) { t = a; a = b; b = t; }
-#undef DVR_KEY_LESS
-    l1 = a;
-    l2 = b;
-    l3 = c;
+    const float u = t * t;
+    float r = 0.0024567249f;
+    r = fmaf(r, u, -0.014401361f);
+    r = fmaf(r, u, 0.03978123f);
+    r = fmaf(r, u, -0.07234859f);
+    r = fmaf(r, u, 0.10498947f);
+    r = fmaf(r, u, -0.14161229f);
+    r = fmaf(r, u, 0.19985907f);
+    r = fmaf(r, u, -0.33332598f);
+    r = fmaf(r, u, 0.9999999f);
+    return t * r;
 }
 
-// Frangi bright-tube vesselness of magnitude-sorted eigenvalues.
-__device__ __forceinline__ float frangi(float l1, float l2, float l3, float inv2a2, float inv2b2, float inv2c2)
+__device__ __forceinline__ void eig_sym3(const float A[6], float &mu0, float &mu1, float &mu2)
 {
-    if (l2 >= 0.f || l3 >= 0.f) return 0.f;
-    // quotients through the hardware reciprocal (1 ulp) instead of IEEE division sequences
-    const float Ra2 = (l2 * l2) * __builtin_amdgcn_rcpf(l3 * l3);
-    const float Rb2 = (l1 * l1) * __builtin_amdgcn_rcpf(fabsf(l2 * l3));
-    const float S2 = l1 * l1 + l2 * l2 + l3 * l3;
-    return (-expm1f(-Ra2 * inv2a2)) * expf(-Rb2 * inv2b2) * (-expm1f(-S2 * inv2c2));
+    const float m = (A[0] + A[1] + A[2]) * (1.f / 3.f);
+    const float e00 = A[0] - m, e11 = A[1] - m, e22 = A[2] - m;
+    const float sc = fmaxf(fmaxf(fmaxf(fabsf(e00), fabsf(e11)), fmaxf(fabsf(e22), fabsf(A[3]))),
+                           fmaxf(fabsf(A[4]), fabsf(A[5])));
+    if (!(sc > 0.f)) {
+        mu0 = mu1 = mu2 = m;
+        return;
+    }
+    const float is = __builtin_amdgcn_rcpf(sc);
+    const float b00 = e00 * is, b11 = e11 * is, b22 = e22 * is, b01 = A[3] * is, b02 = A[4] * is, b12 = A[5] * is;
+    const float c00 = fmaf(b00, b00, fmaf(b01, b01, b02 * b02));
+    const float c11 = fmaf(b01, b01, fmaf(b11, b11, b12 * b12));
+    const float c22 = fmaf(b02, b02, fmaf(b12, b12, b22 * b22));
+    const float c01 = fmaf(b00, b01, fmaf(b01, b11, b02 * b12));
+    const float c02 = fmaf(b00, b02, fmaf(b01, b12, b02 * b22));
+    const float c12 = fmaf(b01, b02, fmaf(b11, b12, b12 * b22));
+    const float J2 = 0.5f * (c00 + c11 + c22);
+    const float M0 = fmaf(c00, b22 - b11, fmaf(c11, b00 - b22, c22 * (b11 - b00)));
+    const float db[3] = {b11 - b00, b22 - b00, b22 - b11};
+    const float dc[3] = {c11 - c00, c22 - c00, c22 - c11};
+    const float bo[3] = {b01, b02, b12}, co[3] = {c01, c02, c12};
+    float sB = 0.f;
+#pragma unroll
+    for (int q = 0; q < 3; ++q)
+#pragma unroll
+        for (int k = 0; k < 3; ++k) {
+            const float t = fmaf(co[k], db[q], -bo[k] * dc[q]);
+            sB = fmaf(t, t, sB);
+        }
+    const float t0 = fmaf(b01, c02, -b02 * c01), t1 = fmaf(b01, c12, -b12 * c01), t2 = fmaf(b02, c12, -b12 * c02);
+    const float sC = fmaf(t0, t0, fmaf(t1, t1, t2 * t2));
+    const float D = fmaf(M0, M0, fmaf(2.f, sB, 12.f * sC));
+    const float J3 = b00 * fmaf(b11, b22, -b12 * b12) - b01 * fmaf(b01, b22, -b12 * b02) + b02 * fmaf(b01, b12, -b11 * b02);
+    // 3 theta = atan2(y, x), y >= 0
+    const float y = sqrtf(D), x = 5.196152422706632f * J3;
+    const float ax = fabsf(x), lo = fminf(ax, y), hi = fmaxf(ax, y);
+    float a = hi > 0.f ? atan01(lo * __builtin_amdgcn_rcpf(hi)) : 0.f;
+    if (y > ax) a = 1.5707963267948966f - a;
+    if (x < 0.f) a = 3.141592653589793f - a;
+    const float th = a * (1.f / 3.f), v = th * th;
+    float sn = 2.6811283e-06f;
+    sn = fmaf(sn, v, -0.00019833124f);
+    sn = fmaf(sn, v, 0.008333295f);
+    sn = fmaf(sn, v, -0.16666666f);
+    sn = fmaf(sn, v, 1.f);
+    sn *= th;
+    float cs = 2.405656e-05f;
+    cs = fmaf(cs, v, -0.0013881775f);
+    cs = fmaf(cs, v, 0.04166639f);
+    cs = fmaf(cs, v, -0.49999997f);
+    cs = fmaf(cs, v, 1.f);
+    const float p = sc * sqrtf(J2 * (1.f / 3.f));
+    mu2 = fmaf(2.f * p, cs, m);
+    const float ps = 1.7320508075688772f * p * sn, pc = p * cs;
+    mu0 = m - (pc + ps);
+    mu1 = m - (pc - ps);
+}
+
+// FP64 re-solve of a near-degenerate spectrum: cyclic Jacobi rotations (each zeroes one
+// off-diagonal entry), backward stable whatever the clustering of the roots (the characteristic
+// polynomial of a near-triple root is too ill-conditioned to solve, even in FP64), and with no
+// transcendental functions, so it stays light in registers.  Returned in ascending order.
+__device__ __forceinline__ void eig_jacobi64(const float A[6], float &mu0, float &mu1, float &mu2)
+{
+    double d[3] = {A[0], A[1], A[2]};
+    double o01 = A[3], o02 = A[4], o12 = A[5];
+    // rotation in the (p, q) plane zeroing a_pq; r is the third index, a_rp and a_rq rotate with it
+    auto rot = [&](double &app, double &aqq, double &apq, double &arp, double &arq) {
+        if (apq == 0.0) return;
+        const double th = (aqq - app) / (2.0 * apq);
+        const double t = (th >= 0.0 ? 1.0 : -1.0) / (fabs(th) + sqrt(fma(th, th, 1.0)));
+        const double c = 1.0 / sqrt(fma(t, t, 1.0)), sn = t * c;
+        app -= t * apq;
+        aqq += t * apq;
+        apq = 0.0;
+        const double rp = arp, rq = arq;
+        arp = c * rp - sn * rq;
+        arq = sn * rp + c * rq;
+    };
+    for (int sweep = 0; sweep < 6; ++sweep) {
+        const double off = fabs(o01) + fabs(o02) + fabs(o12);
+        if (off <= 1e-17 * (fabs(d[0]) + fabs(d[1]) + fabs(d[2]))) break;
+        rot(d[0], d[1], o01, o02, o12);  // (p, q, r) = (0, 1, 2): a_r0 = a02, a_r1 = a12
+        rot(d[0], d[2], o02, o01, o12);  // (0, 2, 1): a_r0 = a01, a_r2 = a12
+        rot(d[1], d[2], o12, o01, o02);  // (1, 2, 0): a_r1 = a01, a_r2 = a02
+    }
+    const double lo = fmin(d[0], fmin(d[1], d[2])), hi = fmax(d[0], fmax(d[1], d[2]));
+    mu0 = (float)lo;
+    mu1 = (float)(d[0] + d[1] + d[2] - lo - hi);
+    mu2 = (float)hi;
+}
+
+// 1 - exp(-x) for x >= 0 with a relative error of a few ulps: a series below 1/16, else the
+// hardware exp2 (where the difference no longer cancels)
+__device__ __forceinline__ float om_exp(float x)
+{
+    if (x < 0.0625f) {
+        float t = fmaf(-x, 1.f / 7.f, 1.f);
+        t = fmaf(-x * (1.f / 6.f), t, 1.f);
+        t = fmaf(-x * (1.f / 5.f), t, 1.f);
+        t = fmaf(-x * (1.f / 4.f), t, 1.f);
+        t = fmaf(-x * (1.f / 3.f), t, 1.f);
+        t = fmaf(-x * 0.5f, t, 1.f);
+        return x * t;
+    }
+    return 1.f - __builtin_amdgcn_exp2f(-x * 1.4426950408889634f);
+}
+
+// Frangi's bright-tube vesselness of sigma^2 H (A, FP32) from its eigenvalues in ascending order.
+// Sorted by (|lambda|, lambda) the eigenvalues are l1, l2, l3 with V != 0 only where l2 < 0 and
+// l3 < 0: in value order mu0 <= mu1 <= mu2 that is exactly mu1 < 0 and mu1 + mu2 < 0, and then
+// l3 = mu0, l2 = mu1, l1 = mu2.  The eigenvalues are re-solved in FP64 when their smallest gap is
+// below tau max|mu|.  ia, ib, ic: 1 / (2 alpha^2), 1 / (2 beta^2), 1 / (2 c^2).
+__device__ __forceinline__ float vesselness(const float A[6], float tau, float ia, float ib, float ic)
+{
+    float mu0, mu1, mu2;
+    eig_sym3(A, mu0, mu1, mu2);
+    const float gap = fminf(mu2 - mu1, mu1 - mu0);
+    const float scl = fmaxf(fabsf(mu0), fabsf(mu2));
+    if (gap < tau * scl) eig_jacobi64(A, mu0, mu1, mu2);
+    if (!(mu1 < 0.f && mu1 + mu2 < 0.f)) return 0.f;
+    const float Ra2 = (mu1 * mu1) * __builtin_amdgcn_rcpf(mu0 * mu0);
+    const float Rb2 = (mu2 * mu2) * __builtin_amdgcn_rcpf(mu0 * mu1);
+    const float S2 = fmaf(mu0, mu0, fmaf(mu1, mu1, mu2 * mu2));
+    return om_exp(Ra2 * ia) * __builtin_amdgcn_exp2f(-Rb2 * ib * 1.4426950408889634f) * om_exp(S2 * ic);
 }
 
 // ------------------------------------------------------------------------------------------------
@@ -239,93 +360,175 @@ __device__ __forceinline__ void zpass_voxel(const void *__restrict__ vol, float 
     ws[2u * N + i] = o.d2;
 }
 
-// Per-voxel epilogue: from the Hessian H of the smoothed volume (Hxx, Hyy, Hzz, Hxy, Hxz, Hyz) and,
-// on the first scale, the intensities In = (I, I[x+1], I[x-1], I[y+1], I[y-1], I[z+1], I[z-1])
-// (clamped neighbours): the gradient (Eq. 2), k (Eq. 3), the eigenvalues of sigma^2 H and V.
-// Updates vmax with this voxel's |g| (first scale) or |sigma^2 H|_F (Frangi-c pass).
-template <int OUT_DT, int LAYOUT>
-__device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const float H[6], const float In[7], uint32_t v,
-                                          uint32_t N, float &vmax)
+// LDS floats of the workgroup's compaction list: the six entries of sigma^2 H of up to NT NV voxels
+// (then each one's V in the first row), and the waves' counts
+template <int NV>
+struct Compact {
+    static constexpr int kSlots = NT * NV;
+    static constexpr int kFloats = 6 * kSlots + NT / 64;
+};
+
+// Epilogue of the NV voxels of one lane (every lane of the wave calls it, with the same NV): from the
+// Hessian H of the smoothed volume (Hxx, Hyy, Hzz, Hxy, Hxz, Hyz) and, on the first scale, the
+// intensities In = (I, I[x+1], I[x-1], I[y+1], I[y-1], I[z+1], I[z-1]) (clamped neighbours): the
+// gradient (Eq. 2), k (Eq. 3), the eigenvalues of sigma^2 H and V.  Updates vmax with |g| (first
+// scale) or |sigma^2 H|_F (Frangi-c pass).
+// V can be non-zero only where tr(sigma^2 H) < 0 (it needs the two eigenvalues of largest magnitude
+// negative), so only those voxels take the eigen-solve and Frangi: the workgroup writes them to one
+// list in the LDS area cw (Compact<NV>::kFloats floats), solves the list densely, one voxel per
+// lane, and reads the results back.  Elsewhere V = 0 exactly, as the full evaluation would give.
+// Every thread of the workgroup must call it (it holds barriers).
+template <int OUT_DT, int LAYOUT, int NV>
+__device__ __forceinline__ void voxels_out(const XYArgs &a, float sigma2, const float (&H)[NV][6],
+                                           const float (&In)[NV][7], const uint32_t (&v)[NV], const bool (&live)[NV],
+                                           uint32_t N, float &vmax, float *cw, const float (*Vprev)[NV] = nullptr)
 {
     if constexpr (LAYOUT == kHessianOut) {
         // the adjoint's recomputation: H itself, [6][N] FP32 in a.grad
         float *Ho = reinterpret_cast<float *>(a.grad);
 #pragma unroll
-        for (int e = 0; e < 6; ++e) Ho[(size_t)e * N + v] = H[e];
+        for (int i = 0; i < NV; ++i)
+            if (live[i])
+#pragma unroll
+                for (int e = 0; e < 6; ++e) Ho[(size_t)e * N + v[i]] = H[i][e];
         return;
     }
-    float A[6];
-    for (int e = 0; e < 6; ++e) A[e] = sigma2 * H[e];
+    float A[NV][6];
+#pragma unroll
+    for (int i = 0; i < NV; ++i)
+#pragma unroll
+        for (int e = 0; e < 6; ++e) A[i][e] = sigma2 * H[i][e];
     if (a.fro_pass) {
-        const float f2 = A[0] * A[0] + A[1] * A[1] + A[2] * A[2] + 2.f * (A[3] * A[3] + A[4] * A[4] + A[5] * A[5]);
-        vmax = fmaxf(vmax, sqrtf(f2));
+#pragma unroll
+        for (int i = 0; i < NV; ++i) {
+            const float f2 = A[i][0] * A[i][0] + A[i][1] * A[i][1] + A[i][2] * A[i][2] +
+                             2.f * (A[i][3] * A[i][3] + A[i][4] * A[i][4] + A[i][5] * A[i][5]);
+            if (live[i]) vmax = fmaxf(vmax, sqrtf(f2));
+        }
         return;
     }
-    float gx_ = 0.f, gy_ = 0.f, gz_ = 0.f, kap = 0.f;
-    const float Ival = In[0];
-    if (a.first) {
-        gx_ = (In[1] - In[2]) * a.inv2h[0];
-        gy_ = (In[3] - In[4]) * a.inv2h[1];
-        gz_ = (In[5] - In[6]) * a.inv2h[2];
+    // V: the voxels that can have V != 0, compacted over the workgroup (a list per wave would leave
+    // the lanes of a second round mostly idle)
+    constexpr int NW = NT / 64;
+    const int wv = threadIdx.x >> 6;
+    bool need[NV];
+    int slot[NV];
+    int wcount = 0;
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        need[i] = live[i] && (A[i][0] + A[i][1] + A[i][2] < 0.f);
+        const uint64_t m = __ballot(need[i]);
+        slot[i] = wcount + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
+        wcount += __popcll(m);
+    }
+    int *cnt = reinterpret_cast<int *>(cw + 6 * Compact<NV>::kSlots);
+    if ((threadIdx.x & 63) == 0) cnt[wv] = wcount;
+    __syncthreads();
+    int base = 0, count = 0;
+#pragma unroll
+    for (int w = 0; w < NW; ++w) {
+        const int c = cnt[w];
+        base += (w < wv) ? c : 0;
+        count += c;
+    }
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        slot[i] += base;
+        if (need[i])
+#pragma unroll
+            for (int e = 0; e < 6; ++e) cw[e * Compact<NV>::kSlots + slot[i]] = A[i][e];
+    }
+    // everything but V first (the gradient and k of the first scale), so that H and the intensities
+    // are dead before the eigen-solves
+    float kap_keep[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        kap_keep[i] = 0.f;
+        if (!live[i] || !a.first) continue;
+        float gx_, gy_, gz_, kap = 0.f;
+        gx_ = (In[i][1] - In[i][2]) * a.inv2h[0];
+        gy_ = (In[i][3] - In[i][4]) * a.inv2h[1];
+        gz_ = (In[i][5] - In[i][6]) * a.inv2h[2];
         vmax = fmaxf(vmax, sqrtf(gx_ * gx_ + gy_ * gy_ + gz_ * gz_));
         const float gm = fmaxf(fabsf(gx_), fmaxf(fabsf(gy_), fabsf(gz_)));
         if (gm > 0.f) {
             const float ig = __builtin_amdgcn_rcpf(gm);
             const float u0 = gx_ * ig, u1 = gy_ * ig, u2 = gz_ * ig;
-            const float num = H[0] * u0 * u0 + H[1] * u1 * u1 + H[2] * u2 * u2 +
-                              2.f * (H[3] * u0 * u1 + H[4] * u0 * u2 + H[5] * u1 * u2);
+            const float num = H[i][0] * u0 * u0 + H[i][1] * u1 * u1 + H[i][2] * u2 * u2 +
+                              2.f * (H[i][3] * u0 * u1 + H[i][4] * u0 * u2 + H[i][5] * u1 * u2);
             kap = num * __builtin_amdgcn_rcpf(u0 * u0 + u1 * u1 + u2 * u2);  // the sum is >= 1
         }
-    }
-    float l1, l2, l3;
-    eig_sorted(A, a.tau, l1, l2, l3);
-    float c = a.c_host;
-    if (!(c > 0.f)) {
-        c = 0.5f * __hip_atomic_load(a.fro, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        if (!(c > 0.f)) c = 1.f;
-    }
-    float V = frangi(l1, l2, l3, a.inv2a2, a.inv2b2, 0.5f * __builtin_amdgcn_rcpf(c * c));
-    if constexpr (LAYOUT == DVR_PLANAR) {
-        if (!a.first) V = fmaxf(V, ldo<OUT_DT>(a.ves, v));
-        else {
-            st<OUT_DT>(a.grad, v, gx_);
-            st<OUT_DT>(a.grad, N + v, gy_);
-            st<OUT_DT>(a.grad, 2u * N + v, gz_);
-            st<OUT_DT>(a.kappa, v, kap);
-        }
-        st<OUT_DT>(a.ves, v, V);
-    } else if constexpr (LAYOUT == DVR_SPLIT) {
-        if (!a.first) V = fmaxf(V, ldo<OUT_DT>(a.ves, v));
-        else if constexpr (OUT_DT == DVR_F32) {
-            reinterpret_cast<float4 *>(a.grad)[v] = make_float4(gx_, gy_, gz_, kap);
+        const uint32_t vi = v[i];
+        if constexpr (LAYOUT == DVR_PLANAR) {
+            st<OUT_DT>(a.grad, vi, gx_);
+            st<OUT_DT>(a.grad, N + vi, gy_);
+            st<OUT_DT>(a.grad, 2u * N + vi, gz_);
+            st<OUT_DT>(a.kappa, vi, kap);
+        } else if constexpr (LAYOUT == DVR_SPLIT) {
+            if constexpr (OUT_DT == DVR_F32) {
+                reinterpret_cast<float4 *>(a.grad)[vi] = make_float4(gx_, gy_, gz_, kap);
+            } else {
+                union { __half h[4]; uint2 u; } rec;
+                rec.h[0] = __float2half_rn(gx_);
+                rec.h[1] = __float2half_rn(gy_);
+                rec.h[2] = __float2half_rn(gz_);
+                rec.h[3] = __float2half_rn(kap);
+                reinterpret_cast<uint2 *>(a.grad)[vi] = rec.u;
+            }
         } else {
-            union { __half h[4]; uint2 u; } rec;
-            rec.h[0] = __float2half_rn(gx_);
-            rec.h[1] = __float2half_rn(gy_);
-            rec.h[2] = __float2half_rn(gz_);
-            rec.h[3] = __float2half_rn(kap);
-            reinterpret_cast<uint2 *>(a.grad)[v] = rec.u;
+            // interleaved: (I, gx, gy, gz) now, (k, V, 0, 0) with V below
+            if constexpr (OUT_DT == DVR_F32) {
+                reinterpret_cast<float4 *>(a.grad)[2u * vi] = make_float4(In[i][0], gx_, gy_, gz_);
+            } else {
+                union { __half h[4]; uint2 u; } rec;
+                rec.h[0] = __float2half_rn(In[i][0]);
+                rec.h[1] = __float2half_rn(gx_);
+                rec.h[2] = __float2half_rn(gy_);
+                rec.h[3] = __float2half_rn(gz_);
+                reinterpret_cast<uint2 *>(a.grad)[2u * vi] = rec.u;
+            }
+            kap_keep[i] = kap;
         }
-        st<OUT_DT>(a.ves, v, V);
-    } else {
-        if (!a.first) {
-            V = fmaxf(V, ldo<OUT_DT>(a.grad, 8u * v + 5u));
-            st<OUT_DT>(a.grad, 8u * v + 5u, V);
-        } else if constexpr (OUT_DT == DVR_F32) {
-            float4 *r = reinterpret_cast<float4 *>(a.grad) + 2u * v;
-            r[0] = make_float4(Ival, gx_, gy_, gz_);
-            r[1] = make_float4(kap, V, 0.f, 0.f);
+    }
+    __syncthreads();
+    if (count > 0) {
+        float c = a.c_host;
+        if (!(c > 0.f)) {
+            c = 0.5f * __hip_atomic_load(a.fro, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            if (!(c > 0.f)) c = 1.f;
+        }
+        const float ic = 0.5f * __builtin_amdgcn_rcpf(c * c);
+        for (int s = threadIdx.x; s < count; s += NT) {
+            float Ai[6];
+#pragma unroll
+            for (int e = 0; e < 6; ++e) Ai[e] = cw[e * Compact<NV>::kSlots + s];
+            cw[s] = vesselness(Ai, a.tau, a.inv2a2, a.inv2b2, ic);
+        }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        if (!live[i]) continue;
+        float V = need[i] ? cw[slot[i]] : 0.f;
+        const uint32_t vi = v[i];
+        // V of the earlier scales: given by the caller (loaded ahead), or read here
+        if constexpr (LAYOUT == DVR_PLANAR || LAYOUT == DVR_SPLIT) {
+            if (!a.first) V = fmaxf(V, Vprev ? (*Vprev)[i] : ldo<OUT_DT>(a.ves, vi));
+            st<OUT_DT>(a.ves, vi, V);
         } else {
-            union { __half h[8]; uint4 u; } rec;
-            rec.h[0] = __float2half_rn(Ival);
-            rec.h[1] = __float2half_rn(gx_);
-            rec.h[2] = __float2half_rn(gy_);
-            rec.h[3] = __float2half_rn(gz_);
-            rec.h[4] = __float2half_rn(kap);
-            rec.h[5] = __float2half_rn(V);
-            rec.h[6] = __float2half_rn(0.f);
-            rec.h[7] = __float2half_rn(0.f);
-            reinterpret_cast<uint4 *>(a.grad)[v] = rec.u;
+            if (!a.first) {
+                V = fmaxf(V, Vprev ? (*Vprev)[i] : ldo<OUT_DT>(a.grad, 8u * vi + 5u));
+                st<OUT_DT>(a.grad, 8u * vi + 5u, V);
+            } else if constexpr (OUT_DT == DVR_F32) {
+                reinterpret_cast<float4 *>(a.grad)[2u * vi + 1u] = make_float4(kap_keep[i], V, 0.f, 0.f);
+            } else {
+                union { __half h[4]; uint2 u; } rec;
+                rec.h[0] = __float2half_rn(kap_keep[i]);
+                rec.h[1] = __float2half_rn(V);
+                rec.h[2] = __float2half_rn(0.f);
+                rec.h[3] = __float2half_rn(0.f);
+                reinterpret_cast<uint2 *>(a.grad)[2u * vi + 1u] = rec.u;
+            }
         }
     }
 }
@@ -333,7 +536,7 @@ __device__ __forceinline__ void voxel_out(const XYArgs &a, float sigma2, const f
 // y and x filters of one TX x TY tile of slice z from the staged z-filtered fields, then the
 // per-voxel epilogue.  Returns this lane's contribution to |g|_max (first scale) or to
 // max |sigma^2 H|_F (Frangi-c pass); the caller reduces it.  lds holds
-// (3 (TY + 2 Ry) + 6 TY) (TX + 2 Rx) floats.  The taps may live in any address space (kernel
+// xy_lds_floats<TX, TY>(Rx, Ry) floats.  The taps may live in any address space (kernel
 // arguments, or a device table read through the constant address space by the batched kernel).
 template <int DT, int OUT_DT, int LAYOUT, int TX, int TY, typename ST>
 __device__ __forceinline__ float xy_tile(const XYArgs &a, const ST &taps, int x0, int y0, int z, float *lds)
@@ -342,8 +545,9 @@ __device__ __forceinline__ float xy_tile(const XYArgs &a, const ST &taps, int x0
     const auto &ty = taps.ax[1];
     const int Rx = tx.R, Ry = ty.R;
     const int W = TX + 2 * Rx, HH = TY + 2 * Ry;
-    float *F = lds;                   // [3][HH][W]
-    float *Fy = lds + 3 * HH * W;     // [6][TY][W]
+    constexpr int kCW = Compact<TX * TY / NT>::kFloats;
+    float *F = lds;                                          // [3][HH][W]; the waves' compaction lists after the y filters
+    float *Fy = lds + (3 * HH * W > kCW ? 3 * HH * W : kCW);  // [6][TY][W]
     const int nx = a.nx, ny = a.ny, nz = a.nz;
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
     const uint32_t N = plane * (uint32_t)nz;
@@ -381,36 +585,45 @@ __device__ __forceinline__ float xy_tile(const XYArgs &a, const ST &taps, int x0
     }
     __syncthreads();
 
-    float vmax = 0.f;
-    for (int p = threadIdx.x; p < TX * TY; p += NT) {
+    constexpr int NV = TX * TY / NT;
+    static_assert((TX * TY) % NT == 0, "whole voxels per lane");
+    float H[NV][6], In[NV][7];
+    uint32_t v[NV];
+    bool live[NV];
+#pragma unroll
+    for (int i = 0; i < NV; ++i) {
+        const int p = threadIdx.x + NT * i;
         const int yy = p / TX, xx = p - yy * TX;
         const int gx = x0 + xx, gy = y0 + yy;
-        const bool live = gx < nx && gy < ny;
+        live[i] = gx < nx && gy < ny;
         const int cls = (gx == 0) ? 1 : (gx == nx - 1 ? 2 : 0);
         auto fy = [&](int k) { return [=](int m) { return Fy[k * TY * W + yy * W + xx + Rx + m]; }; };
-        float H[6];
-        H[0] = filtD2(tx, cls, fy(0));   // Hxx = D2x Gy Gz
-        H[3] = filtD1(tx, cls, fy(1));   // Hxy = D1x D1y Gz
-        H[1] = filtG(tx, fy(2));         // Hyy = Gx D2y Gz
-        H[4] = filtD1(tx, cls, fy(3));   // Hxz = D1x Gy D1z
-        H[5] = filtG(tx, fy(4));         // Hyz = Gx D1y D1z
-        H[2] = filtG(tx, fy(5));         // Hzz = Gx Gy D2z
-        if (!live) continue;
-        const uint32_t v = (uint32_t)z * plane + (uint32_t)gy * nx + gx;
-        float In[7] = {0.f, 0.f, 0.f, 0.f, 0.f, 0.f, 0.f};
+        H[i][0] = filtD2(tx, cls, fy(0));   // Hxx = D2x Gy Gz
+        H[i][3] = filtD1(tx, cls, fy(1));   // Hxy = D1x D1y Gz
+        H[i][1] = filtG(tx, fy(2));         // Hyy = Gx D2y Gz
+        H[i][4] = filtD1(tx, cls, fy(3));   // Hxz = D1x Gy D1z
+        H[i][5] = filtG(tx, fy(4));         // Hyz = Gx D1y D1z
+        H[i][2] = filtG(tx, fy(5));         // Hzz = Gx Gy D2z
+        // lanes past the volume edge use an in-range voxel; their results are not stored
+        const int cx = min(gx, nx - 1), cy = min(gy, ny - 1);
+        v[i] = (uint32_t)z * plane + (uint32_t)cy * nx + cx;
+#pragma unroll
+        for (int k = 0; k < 7; ++k) In[i][k] = 0.f;
         if (a.first) {
             Buf b = make_buf(a.vol, N * ElemSize<DT>::v);
-            const uint32_t row = (uint32_t)z * plane + (uint32_t)gy * nx;
-            In[0] = ldv<DT>(b, v);
-            In[1] = ldv<DT>(b, row + clampi(gx + 1, 0, nx - 1));
-            In[2] = ldv<DT>(b, row + clampi(gx - 1, 0, nx - 1));
-            In[3] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(gy + 1, 0, ny - 1) * nx + gx);
-            In[4] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(gy - 1, 0, ny - 1) * nx + gx);
-            In[5] = ldv<DT>(b, (uint32_t)clampi(z + 1, 0, nz - 1) * plane + (uint32_t)gy * nx + gx);
-            In[6] = ldv<DT>(b, (uint32_t)clampi(z - 1, 0, nz - 1) * plane + (uint32_t)gy * nx + gx);
+            const uint32_t row = (uint32_t)z * plane + (uint32_t)cy * nx;
+            In[i][0] = ldv<DT>(b, v[i]);
+            In[i][1] = ldv<DT>(b, row + clampi(cx + 1, 0, nx - 1));
+            In[i][2] = ldv<DT>(b, row + clampi(cx - 1, 0, nx - 1));
+            In[i][3] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(cy + 1, 0, ny - 1) * nx + cx);
+            In[i][4] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(cy - 1, 0, ny - 1) * nx + cx);
+            In[i][5] = ldv<DT>(b, (uint32_t)clampi(z + 1, 0, nz - 1) * plane + (uint32_t)cy * nx + cx);
+            In[i][6] = ldv<DT>(b, (uint32_t)clampi(z - 1, 0, nz - 1) * plane + (uint32_t)cy * nx + cx);
         }
-        voxel_out<OUT_DT, LAYOUT>(a, taps.sigma2, H, In, v, N, vmax);
     }
+    // the staged fields are dead after the y filters (the barrier above): the compaction list reuses them
+    float vmax = 0.f;
+    voxels_out<OUT_DT, LAYOUT, NV>(a, taps.sigma2, H, In, v, live, N, vmax, F);
     return vmax;
 }
 
@@ -493,122 +706,238 @@ __device__ __forceinline__ Line3 r3(const AxisTaps &t, int cls, F &&v)
 // for latency: the intensity loads of the gradient go out first, then every staging load of the
 // z-filtered fields (tile plus halo) before any LDS store, and the y-filter work is spread over all
 // lanes.  One tile per workgroup (no leading barrier).
+// a float in LDS, addressed with a 32-bit pointer (reads through it are LDS instructions)
+typedef __attribute__((address_space(3))) float lds_f;
+
 template <int R, int TX, int TY>
 struct XYTileR {
     static constexpr int W = TX + 2 * R, HH = TY + 2 * R;
     static constexpr int NST = 3 * HH * W;  // staged values
     static constexpr int NFY = 6 * TY * W;  // y-filtered values
+    static constexpr int NCW = Compact<TX * TY / NT>::kFloats;  // the workgroup's compaction list
+    static constexpr int NF = NST > NCW ? NST : NCW;  // the staging area, reused by the lists
 };
 
+// One 64 x TY tile of the fixed-radius pass, for a run of z slices: the loads of a slice (its staged
+// z-filtered fields with halo, the intensities of the gradient and, after the first scale, the V so
+// far) are issued into registers while the previous slice is computed.
 template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY>
-__device__ __forceinline__ float xy_tile_r(const XYArgs &a, const ScaleTaps &taps, int x0, int y0, int z, float *F,
-                                           float *Fy)
-{
+struct XYSlab {
     using T = XYTileR<R, TX, TY>;
-    constexpr int W = T::W, HH = T::HH, NST = T::NST;
-    constexpr int PER = (NST + NT - 1) / NT;
-    constexpr int NV = TX * TY / NT;
-    static_assert((TX * TY) % NT == 0, "whole voxels per lane");
-    const AxisTaps &tx = taps.ax[0];
-    const AxisTaps &ty = taps.ax[1];
-    const int nx = a.nx, ny = a.ny, nz = a.nz;
-    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t N = plane * (uint32_t)nz;
-    const int t = threadIdx.x;
+    static constexpr int W = T::W, HH = T::HH;
+    static constexpr int NW = NT / 64;    // waves
+    static constexpr int NV = TY / NW;    // voxels per lane: rows wv, wv + NW, ... of the tile, x = lane
+    static_assert(TX == 64 && TY % NW == 0 && W <= 128, "one tile column per lane, whole rows per wave");
+    static constexpr int NROW = 3 * HH;   // staged rows (three fields)
+    static constexpr int RPW = (NROW + NW - 1) / NW;
 
+    const XYArgs &a;
+    const ScaleTaps &taps;
+    float *F, *Fy;
+    int x0, y0, nx, ny, nz;
+    uint32_t plane, N;
+    int lane, wv, gx, cx, c0, c1;
+    bool two;
+    // the slice in flight: staged rows, gradient intensities, V of the earlier scales
+    float v0[RPW], v1[RPW];
     float In[NV][7];
-    if (a.first) {
-        Buf b = make_buf(a.vol, N * ElemSize<DT>::v);
+    float Vp[NV];
+
+    __device__ __forceinline__ XYSlab(const XYArgs &a_, const ScaleTaps &t_, float *F_, float *Fy_, int x0_, int y0_)
+        : a(a_), taps(t_), F(F_), Fy(Fy_), x0(x0_), y0(y0_)
+    {
+        nx = a.nx;
+        ny = a.ny;
+        nz = a.nz;
+        plane = (uint32_t)nx * (uint32_t)ny;
+        N = plane * (uint32_t)nz;
+        lane = threadIdx.x & 63;
+        // the wave index is uniform across the wave: row bases stay in scalar registers
+        wv = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+        gx = x0 + lane;              // this lane's output column
+        cx = min(gx, nx - 1);        // lanes past the edge read an in-range voxel (not stored)
+        c0 = clampi(x0 - R + lane, 0, nx - 1);
+        c1 = clampi(x0 - R + 64 + lane, 0, nx - 1);
+        two = 64 + lane < W;
+    }
+
+    // issue the loads of slice z
+    __device__ __forceinline__ void load(int z)
+    {
+        // staged rows: wave wv takes rows wv, wv + NW, ...; a row is W consecutive (clamped) columns,
+        // columns lane and 64 + lane, so each row adds only a scalar base to the column offsets
+#pragma unroll
+        for (int k = 0; k < RPW; ++k) {
+            const int r = wv + NW * k;
+            v0[k] = v1[k] = 0.f;
+            if (NROW % NW == 0 || r < NROW) {
+                const int f = r / HH, yy = r - f * HH;
+                const int gy = clampi(y0 - R + yy, 0, ny - 1);
+                const float *row = a.ws + (size_t)f * N + (size_t)z * plane + (size_t)gy * nx;
+                v0[k] = row[c0];
+                if (two) v1[k] = row[c1];
+            }
+        }
+        if (a.first) {
+            const Buf b = make_buf(a.vol, N * ElemSize<DT>::v);
+            const int xp = min(cx + 1, nx - 1), xm = max(cx - 1, 0);
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+                const int gy = min(y0 + wv + NW * i, ny - 1);
+                const uint32_t row = (uint32_t)z * plane + (uint32_t)gy * nx;
+                const uint32_t rp = (uint32_t)z * plane + (uint32_t)min(gy + 1, ny - 1) * nx;
+                const uint32_t rm = (uint32_t)z * plane + (uint32_t)max(gy - 1, 0) * nx;
+                const uint32_t zp = (uint32_t)min(z + 1, nz - 1) * plane + (uint32_t)gy * nx;
+                const uint32_t zm = (uint32_t)max(z - 1, 0) * plane + (uint32_t)gy * nx;
+                In[i][0] = ldv<DT>(b, row + cx);
+                In[i][1] = ldv<DT>(b, row + xp);
+                In[i][2] = ldv<DT>(b, row + xm);
+                In[i][3] = ldv<DT>(b, rp + cx);
+                In[i][4] = ldv<DT>(b, rm + cx);
+                In[i][5] = ldv<DT>(b, zp + cx);
+                In[i][6] = ldv<DT>(b, zm + cx);
+                Vp[i] = 0.f;
+            }
+        } else {
+#pragma unroll
+            for (int i = 0; i < NV; ++i) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) In[i][k] = 0.f;
+                Vp[i] = 0.f;
+                if constexpr (LAYOUT == DVR_PLANAR || LAYOUT == DVR_SPLIT || LAYOUT == DVR_INTERLEAVED) {
+                    const int gy = min(y0 + wv + NW * i, ny - 1);
+                    const uint32_t vi = (uint32_t)z * plane + (uint32_t)gy * nx + cx;
+                    if constexpr (LAYOUT == DVR_INTERLEAVED) Vp[i] = ldo<OUT_DT>(a.grad, 8u * vi + 5u);
+                    else Vp[i] = ldo<OUT_DT>(a.ves, vi);
+                }
+            }
+        }
+    }
+
+    // write the staged rows of the slice in flight to LDS (all F readers of the previous slice done)
+    __device__ __forceinline__ void store()
+    {
+#pragma unroll
+        for (int k = 0; k < RPW; ++k) {
+            const int r = wv + NW * k;
+            if (NROW % NW == 0 || r < NROW) {
+                F[r * W + lane] = v0[k];
+                if (two) F[r * W + 64 + lane] = v1[k];
+            }
+        }
+    }
+
+    // the filters and the epilogue of slice z from the staged rows in F, with that slice's intensities
+    // and earlier V (In, Vp: copies taken before the next slice's loads were issued)
+    __device__ __forceinline__ float compute(int z, const float (&Ic)[NV][7], const float (&Vc)[NV])
+    {
+        const AxisTaps &tx = taps.ax[0];
+        const AxisTaps &ty = taps.ax[1];
+        const int t = threadIdx.x;
+        // y filters: all TY rows x W columns of the tile; interior sums everywhere, then the one-sided
+        // forms on the first and last row of the volume
+        for (int p = t; p < TY * W; p += NT) {
+            const int yy = p / W, xx = p - yy * W;
+            // one opaque LDS base per position: every tap's offset is then an immediate of its LDS read
+            const lds_f *b = (const lds_f *)(F) + (yy * W + xx);
+            asm volatile("" : "+v"(b));
+            auto f0 = [&](int m) { return b[(0 * HH + R + m) * W]; };
+            auto f1 = [&](int m) { return b[(1 * HH + R + m) * W]; };
+            auto f2 = [&](int m) { return b[(2 * HH + R + m) * W]; };
+            const Line3 r0 = r3<R>(ty, 0, f0);   // Gy Gz, D1y Gz, D2y Gz
+            const float r1g = rG<R>(ty, f1);      // Gy D1z
+            const float r1d = rD1<R>(ty, 0, f1);  // D1y D1z
+            const float r2 = rG<R>(ty, f2);       // Gy D2z
+            Fy[0 * TY * W + p] = r0.g;
+            Fy[1 * TY * W + p] = r0.d1;
+            Fy[2 * TY * W + p] = r0.d2;
+            Fy[3 * TY * W + p] = r1g;
+            Fy[4 * TY * W + p] = r1d;
+            Fy[5 * TY * W + p] = r2;
+        }
+        // the first and last row of the volume take the one-sided differences: only tiles that hold one
+        // (a workgroup-uniform test) redo their difference fields there, each position by the lane that
+        // computed it above
+        if (y0 == 0 || y0 + TY >= ny) {
+            for (int p = t; p < TY * W; p += NT) {
+                const int yy = p / W, xx = p - yy * W;
+                const int gy = y0 + yy;
+                auto f0 = [&](int m) { return F[(0 * HH + yy + R + m) * W + xx]; };
+                auto f1 = [&](int m) { return F[(1 * HH + yy + R + m) * W + xx]; };
+                // two branches with the class a constant (a class chosen at run time would make the
+                // compiler copy both tap sets to vector registers on every path)
+                if (gy == 0) {
+                    Fy[1 * TY * W + p] = rD1<R>(ty, 1, f0);
+                    Fy[2 * TY * W + p] = rD2<R>(ty, 1, f0);
+                    Fy[4 * TY * W + p] = rD1<R>(ty, 1, f1);
+                }
+                if (gy == ny - 1) {
+                    Fy[1 * TY * W + p] = rD1<R>(ty, 2, f0);
+                    Fy[2 * TY * W + p] = rD2<R>(ty, 2, f0);
+                    Fy[4 * TY * W + p] = rD1<R>(ty, 2, f1);
+                }
+            }
+        }
+        __syncthreads();
+
+        // x filters of this lane's voxels (rows wv + NW i, column lane), the same way
+        float H[NV][6];
+        uint32_t v[NV];
+        bool live[NV];
 #pragma unroll
         for (int i = 0; i < NV; ++i) {
-            const int p = t + NT * i;
-            const int yy = p / TX, xx = p - yy * TX;
-            // lanes past the volume edge load an in-range voxel; their results are not stored
-            const int gx = min(x0 + xx, nx - 1), gy = min(y0 + yy, ny - 1);
-            const uint32_t row = (uint32_t)z * plane + (uint32_t)gy * nx;
-            In[i][0] = ldv<DT>(b, row + gx);
-            In[i][1] = ldv<DT>(b, row + clampi(gx + 1, 0, nx - 1));
-            In[i][2] = ldv<DT>(b, row + clampi(gx - 1, 0, nx - 1));
-            In[i][3] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(gy + 1, 0, ny - 1) * nx + gx);
-            In[i][4] = ldv<DT>(b, (uint32_t)z * plane + (uint32_t)clampi(gy - 1, 0, ny - 1) * nx + gx);
-            In[i][5] = ldv<DT>(b, (uint32_t)clampi(z + 1, 0, nz - 1) * plane + (uint32_t)gy * nx + gx);
-            In[i][6] = ldv<DT>(b, (uint32_t)clampi(z - 1, 0, nz - 1) * plane + (uint32_t)gy * nx + gx);
+            const int yy = wv + NW * i;
+            const int gy = y0 + yy;
+            live[i] = gx < nx && gy < ny;
+            // one opaque base per field at the start of the lane's window: every tap's offset then fits
+            // the paired LDS reads' immediates
+            const lds_f *b[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) {
+                b[k] = (const lds_f *)(Fy) + (k * TY * W + yy * W + lane);
+                asm volatile("" : "+v"(b[k]));
+            }
+            auto fy = [&](int k) { return [=](int m) { return b[k][R + m]; }; };
+            H[i][0] = rD2<R>(tx, 0, fy(0));  // Hxx = D2x Gy Gz
+            H[i][3] = rD1<R>(tx, 0, fy(1));  // Hxy = D1x D1y Gz
+            H[i][1] = rG<R>(tx, fy(2));      // Hyy = Gx D2y Gz
+            H[i][4] = rD1<R>(tx, 0, fy(3));  // Hxz = D1x Gy D1z
+            H[i][5] = rG<R>(tx, fy(4));      // Hyz = Gx D1y D1z
+            H[i][2] = rG<R>(tx, fy(5));      // Hzz = Gx Gy D2z
+            v[i] = (uint32_t)z * plane + (uint32_t)min(gy, ny - 1) * nx + cx;
         }
-    } else {
+        // the first and last column of the volume take the one-sided differences (tiles that hold one)
+        if (x0 == 0 || x0 + TX >= nx) {
 #pragma unroll
-        for (int i = 0; i < NV; ++i)
-#pragma unroll
-            for (int k = 0; k < 7; ++k) In[i][k] = 0.f;
-    }
-
-    // stage the z-filtered fields of the tile and its halo (clamped coordinates)
-    float tmp[PER];
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int p = t + NT * i;
-        tmp[i] = 0.f;
-        if (NST % NT == 0 || p < NST) {
-            const int row = p / W, xx = p - row * W;
-            const int f = row / HH, yy = row - f * HH;
-            const int gy = clampi(y0 - R + yy, 0, ny - 1), gx = clampi(x0 - R + xx, 0, nx - 1);
-            tmp[i] = a.ws[(size_t)f * N + (size_t)z * plane + (size_t)gy * nx + gx];
+            for (int i = 0; i < NV; ++i) {
+                const int yy = wv + NW * i;
+                auto fy = [&](int k) { return [=](int m) { return Fy[k * TY * W + yy * W + lane + R + m]; }; };
+                if (gx == 0) {
+                    H[i][0] = rD2<R>(tx, 1, fy(0));
+                    H[i][3] = rD1<R>(tx, 1, fy(1));
+                    H[i][4] = rD1<R>(tx, 1, fy(3));
+                }
+                if (gx == nx - 1) {
+                    H[i][0] = rD2<R>(tx, 2, fy(0));
+                    H[i][3] = rD1<R>(tx, 2, fy(1));
+                    H[i][4] = rD1<R>(tx, 2, fy(3));
+                }
+            }
         }
+        // the staged fields are dead after the y filters: the compaction lists reuse them
+        float vmax = 0.f;
+        voxels_out<OUT_DT, LAYOUT, NV>(a, taps.sigma2, H, Ic, v, live, N, vmax, F, &Vc);
+        return vmax;
     }
-#pragma unroll
-    for (int i = 0; i < PER; ++i) {
-        const int p = t + NT * i;
-        if (NST % NT == 0 || p < NST) F[p] = tmp[i];
-    }
-    __syncthreads();
+};
 
-    // y filters: all TY rows x W columns of the tile
-    for (int p = t; p < TY * W; p += NT) {
-        const int yy = p / W, xx = p - yy * W;
-        const int gy = y0 + yy;
-        const int cls = (gy == 0) ? 1 : (gy == ny - 1 ? 2 : 0);
-        auto f0 = [&](int m) { return F[(0 * HH + yy + R + m) * W + xx]; };
-        auto f1 = [&](int m) { return F[(1 * HH + yy + R + m) * W + xx]; };
-        auto f2 = [&](int m) { return F[(2 * HH + yy + R + m) * W + xx]; };
-        const Line3 r0 = r3<R>(ty, cls, f0);  // Gy Gz, D1y Gz, D2y Gz
-        const float r1g = rG<R>(ty, f1);       // Gy D1z
-        const float r1d = rD1<R>(ty, cls, f1); // D1y D1z
-        const float r2 = rG<R>(ty, f2);        // Gy D2z
-        Fy[0 * TY * W + p] = r0.g;
-        Fy[1 * TY * W + p] = r0.d1;
-        Fy[2 * TY * W + p] = r0.d2;
-        Fy[3 * TY * W + p] = r1g;
-        Fy[4 * TY * W + p] = r1d;
-        Fy[5 * TY * W + p] = r2;
-    }
-    __syncthreads();
-
-    float vmax = 0.f;
-#pragma unroll
-    for (int i = 0; i < NV; ++i) {
-        const int p = t + NT * i;
-        const int yy = p / TX, xx = p - yy * TX;
-        const int gx = x0 + xx, gy = y0 + yy;
-        const bool live = gx < nx && gy < ny;
-        const int cls = (gx == 0) ? 1 : (gx == nx - 1 ? 2 : 0);
-        auto fy = [&](int k) { return [=](int m) { return Fy[k * TY * W + yy * W + xx + R + m]; }; };
-        float H[6];
-        H[0] = rD2<R>(tx, cls, fy(0));  // Hxx = D2x Gy Gz
-        H[3] = rD1<R>(tx, cls, fy(1));  // Hxy = D1x D1y Gz
-        H[1] = rG<R>(tx, fy(2));        // Hyy = Gx D2y Gz
-        H[4] = rD1<R>(tx, cls, fy(3));  // Hxz = D1x Gy D1z
-        H[5] = rG<R>(tx, fy(4));        // Hyz = Gx D1y D1z
-        H[2] = rG<R>(tx, fy(5));        // Hzz = Gx Gy D2z
-        if (!live) continue;
-        const uint32_t v = (uint32_t)z * plane + (uint32_t)gy * nx + gx;
-        voxel_out<OUT_DT, LAYOUT>(a, taps.sigma2, H, In[i], v, N, vmax);
-    }
-    return vmax;
-}
-
+// LDS floats of the generic tile: the staged fields (whose space the four waves' compaction lists
+// reuse after the y filters) and the y-filtered fields
 template <int TX, int TY>
 __host__ __device__ constexpr size_t xy_lds_floats(int Rx, int Ry)
 {
-    return (size_t)(3 * (TY + 2 * Ry) + 6 * TY) * (size_t)(TX + 2 * Rx);
+    const size_t st = (size_t)3 * (TY + 2 * Ry) * (TX + 2 * Rx), cw = (size_t)Compact<TX * TY / NT>::kFloats;
+    return (st > cw ? st : cw) + (size_t)6 * TY * (TX + 2 * Rx);
 }
 
 }  // namespace dvr

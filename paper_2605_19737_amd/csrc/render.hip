@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
     const RayOut o = march_fwd<LAYOUT, DT, KMAX>(feat, g, sh, kx, rp, invg, r);
     if (valid) {
         const size_t pix = ((size_t)(L.cam_base + cam) * L.H + pj) * L.W + pi;
-        reinterpret_cast<float4 *>(L.out)[pix] = make_float4(o.C0, o.C1, o.C2, 1.f - o.T);
+        reinterpret_cast<float4 *>(L.out)[pix] = make_float4(o.C0, o.C1, o.C2, o.A);
         if (L.T_last) L.T_last[pix] = o.Tprev;
         if (L.k_last) L.k_last[pix] = o.last;
     }

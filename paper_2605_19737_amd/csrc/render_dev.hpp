@@ -474,7 +474,7 @@ __device__ __forceinline__ void eq4(const KRender &rp, float invg, const Chan &c
 // ------------------------------------------------------------------------------------------------
 // One ray, front to back.  Lanes of pixels outside the image pass a ray with N = 0.
 struct RayOut {
-    float C0, C1, C2, T, Tprev;
+    float C0, C1, C2, A, T, Tprev;  // A = sum of T_k alpha_k (= 1 - T in exact arithmetic)
     int last, shaded;
 };
 
@@ -483,7 +483,9 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
                                             const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r)
 {
     RayOut o_;
-    float C0 = 0.f, C1 = 0.f, C2 = 0.f, T = 1.f, Tprev = 1.f;
+    // the opacity is accumulated as a sum of the positive terms T_k alpha_k, relatively accurate
+    // however faint the ray; 1 - T would carry an absolute error of one FP32 ulp of 1
+    float C0 = 0.f, C1 = 0.f, C2 = 0.f, A = 0.f, T = 1.f, Tprev = 1.f;
     int last = -1, shaded = 0;
     if (r.N > 0) {
         Vox<LAYOUT, DT> vx;
@@ -565,6 +567,7 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
                 C0 = fmaf(ta, o.c[0], C0);
                 C1 = fmaf(ta, o.c[1], C1);
                 C2 = fmaf(ta, o.c[2], C2);
+                A += ta;
                 T = T * o.om;
             }
             last = k;
@@ -578,7 +581,7 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
             q[2] += dq[2];
         }
     }
-    o_.C0 = C0; o_.C1 = C1; o_.C2 = C2; o_.T = T; o_.Tprev = Tprev; o_.last = last; o_.shaded = shaded;
+    o_.C0 = C0; o_.C1 = C1; o_.C2 = C2; o_.A = A; o_.T = T; o_.Tprev = Tprev; o_.last = last; o_.shaded = shaded;
     return o_;
 }
 
