@@ -156,7 +156,7 @@ def main():
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     for _ in range(args.steps):
-        step(timing)
+        T_last, k_last = step(timing)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     t_feat = sum(a.elapsed_time(b) for a, b, _ in timing) / 1e3
@@ -170,6 +170,22 @@ def main():
         f"{1e3 * t_rend / args.steps:.2f} ms); samples/step evaluated {evaluated:.4g} shaded {shaded:.4g}; wall {wall:.2f}s")
 
     K = args.steps
+    # gather ceiling: the same rays, samples and loads without the optics (dvr_render_gather), timed
+    # the same way on the same stream; its counters must equal the forward pass's
+    sink = torch.empty((V, 1024, 1024), dtype=torch.float32, device=dev)
+    cg = torch.zeros(2, dtype=torch.int64, device=dev)
+    dvr.render_gather(vol, feats, knots, tf, w.params, cams, k_last, sink=sink, counters=cg)
+    torch.cuda.synchronize()
+    if [int(x) for x in cg.cpu().tolist()] != [evaluated, shaded]:
+        raise RuntimeError(f"gather walk counts {cg.cpu().tolist()} differ from the raymarch's {[evaluated, shaded]}")
+    g0, g1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    g0.record(stream)
+    for _ in range(K):
+        dvr.render_gather(vol, feats, knots, tf, w.params, cams, k_last, sink=sink)
+    g1.record(stream)
+    torch.cuda.synchronize()
+    t_gather = g0.elapsed_time(g1) / 1e3
+    del sink
     samples_per_s = evaluated * K / t_step
     render_sps = evaluated * K / t_rend
     vox_per_s = nvox * K / t_feat
@@ -185,12 +201,23 @@ def main():
                    "write_bytes_per_launch": tr["write_bytes_per_launch"],
                    "hbm_gbs": (tr["fetch_bytes_per_launch"] + tr["write_bytes_per_launch"]) / render_launch_s / 1e9,
                    "views_per_launch": tr.get("views_per_launch"), "source_sha": sha}
-    roofline = {"bound": "alu", "achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_TFLOPS,
-                "unit": "TFLOP/s", "frac": round(achieved_tflops / PEAK_FP32_TFLOPS, 4),
+    # The raymarch is bound by its gathers (texture-path counters), not by HBM bytes or ALU: the
+    # roofline is the measured gather ceiling, the same walk and loads without the optics; the ALU
+    # fraction (shaded and transparent samples at their own flop counts) against the published
+    # FP32 peak stands beside it.
+    gather_sps = evaluated * K / t_gather
+    roofline = {"bound": "gather", "achieved": round(render_sps / 1e9, 3), "peak": round(gather_sps / 1e9, 3),
+                "unit": "Gsamples/s", "frac": round(render_sps / gather_sps, 4),
                 "traffic": traffic, "kernel": "k_render (FP32 quad layout, K<=8)",
                 "avg_launch_ms": round(1e3 * render_launch_s, 4),
-                "flops_per_launch": flops_per_step / launches_per_step,
-                "frac_of_published_fp32_peak": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4)}
+                "gather_kernel": "k_render_gather (same rays, samples and loads; no Eq. 4, exp or compositing)",
+                "gather_avg_launch_ms": round(1e3 * t_gather / (K * launches_per_step), 4),
+                "samples_per_launch": evaluated / launches_per_step,
+                "alu": {"achieved": round(achieved_tflops, 3), "peak": PEAK_FP32_PUBLISHED, "unit": "TFLOP/s",
+                        "frac": round(achieved_tflops / PEAK_FP32_PUBLISHED, 4),
+                        "flops_per_launch": flops_per_step / launches_per_step,
+                        "flop_per_sample": {"shaded": FLOP_SHADED, "transparent": FLOP_TRANSPARENT},
+                        "frac_of_unpacked_fp32_peak": round(achieved_tflops / PEAK_FP32_TFLOPS, 4)}}
 
     comps = {"features_voxels_per_s": vox_per_s, "features_ms": 1e3 * t_feat / K,
              "features_hbm_frac": FEAT_BYTES_F32 * vox_per_s / (PEAK_HBM_GBS * 1e9),
@@ -268,7 +295,9 @@ def main():
         t_cr = time.perf_counter() - t
         s_per_sample = t_cr / max(ro["nsamp"], 1)
         t_cpu_step = t_cf + s_per_sample * evaluated
+        one = cpu_one_thread(oracle, w, v64, of, sp, prm, evaluated, nvox, np, log)
         cpu = {"value": evaluated / t_cpu_step, "unit": "ray-samples/s", "cores": threads, "kind": "oracle",
+               "cpu_model": cpu_model(), "one_thread": one,
                "sample": f"FP64 oracle: full 3-scale feature pass ({t_cf:.2f} s) + {nv_cpu} whole 1024^2 views "
                          f"evenly spaced over the {V} ({ro['nsamp']} samples, {t_cr:.2f} s); step time = features "
                          f"+ per-sample time x the step's {evaluated} evaluated samples",
@@ -284,6 +313,59 @@ def main():
                       "voxels": nvox, "views": V, "image": [1024, 1024]},
            "roofline": roofline, "cpu_baseline": cpu, "components": comps}
     print(json.dumps(out), flush=True)
+
+
+def cpu_model():
+    try:
+        with open("/proc/cpuinfo") as fh:
+            for line in fh:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return None
+
+
+def cpu_one_thread(oracle, w, v64, of, sp, prm, evaluated, nvox, np, log):
+    """The oracle on one thread (OpenMP limited to 1 for the call): the feature pass on a 24-slice
+    slab of the head, scaled to the whole volume, and 2^18 pixels sampled over the views, scaled to the
+    step's evaluated samples (the render sample reads the whole-volume features of)."""
+    import ctypes
+    try:
+        gomp = ctypes.CDLL("libgomp.so.1")
+    except OSError:
+        return None
+    prev = gomp.omp_get_max_threads()
+    gomp.omp_set_num_threads(1)
+    try:
+        z0 = v64.shape[0] // 2 - 12
+        slab = np.ascontiguousarray(v64[z0:z0 + 24])
+        t = time.perf_counter()
+        oracle.features(slab, sp, [float(np.float32(s)) for s in w.sigmas], c=float(np.float32(w.c)))
+        t_f = (time.perf_counter() - t) * nvox / slab.size
+    finally:
+        gomp.omp_set_num_threads(prev)
+    rng = np.random.default_rng(5)
+    M = 1 << 18
+    nv = len(w.cams)
+    cams = [w.cams[(i * nv) // 8] for i in range(min(8, nv))]
+    H, W = cams[0].height, cams[0].width
+    pix = np.stack([rng.integers(0, len(cams), M), rng.integers(0, H, M), rng.integers(0, W, M)], 1).astype(np.int32)
+    gomp.omp_set_num_threads(1)
+    try:
+        t = time.perf_counter()
+        ro = oracle.render(v64, of, of["gmax"], sp, w.tf_knots, w.tf_rgba, prm, cams, pix=pix)
+        t_r = time.perf_counter() - t
+    finally:
+        gomp.omp_set_num_threads(prev)
+    per_sample = t_r / max(ro["nsamp"], 1)
+    value = evaluated / (t_f + per_sample * evaluated)
+    log(f"CPU one thread: features {t_f:.1f} s (scaled), {ro['nsamp']} samples in {t_r:.1f} s")
+    return {"value": value, "unit": "ray-samples/s", "cores": 1,
+            "sample": f"FP64 oracle on one thread: the 3-scale feature pass on 24 of {v64.shape[0]} slices "
+                      f"({t_f * slab.size / nvox:.2f} s, scaled by the voxel count) + {M} pixels sampled over 8 "
+                      f"views ({ro['nsamp']} samples, {t_r:.2f} s, scaled to the step's samples)",
+            "features_voxels_per_s": nvox / t_f, "render_samples_per_s": ro["nsamp"] / t_r}
 
 
 def leg_feature_adjoint(w, vol, feats, knots, tf, cams, stream, dvr, torch, np, log):
@@ -512,8 +594,7 @@ def leg_c5(dev, stream, dvr, torch, np, log):
     out = {"normalize_ms": float(t[0]), "features_ms": float(t[1]), "fwd_ms_per_view": float(t[2]) / 8,
            "bwd_ms_per_view": float(t[3]) / 8, "fwd_bwd_ms_per_view": float(t[2] + t[3]) / 8,
            "features_voxels_per_s": raw.numel() / (t[1] / 1e3), "render_samples_per_s": evaluated / (t[2] / 1e3),
-           # compulsory bytes: normalize reads 2 B twice (reduce, scale) and writes 2 B; the feature pass
-           # reads the 2-byte volume and writes one 16-byte record per voxel
+           # compulsory bytes: normalize reads 2 B twice (reduce, scale) and writes 2 B
            "normalize_hbm_frac": 6 * raw.numel() / (t[0] / 1e3) / (PEAK_HBM_GBS * 1e9),
            "histogram_ms": th, "histogram_hbm_frac": 2 * raw.numel() / (th / 1e3) / (PEAK_HBM_GBS * 1e9),
            "tissue_peaks": pk,
@@ -521,7 +602,8 @@ def leg_c5(dev, stream, dvr, torch, np, log):
            # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz = 3.93e13 32-bit operations per second
            "median3_ms": tdn, "median3_hbm_frac": 4 * raw.numel() / (tdn / 1e3) / (PEAK_HBM_GBS * 1e9),
            "median3_alu_frac": 388.0 * raw.numel() / (tdn / 1e3) / 3.93216e13,
-           "features_hbm_frac": 18 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9),
+           # the feature pass's compulsory bytes: read the 2-byte volume, write g, k, V in FP16 (10 B)
+           "features_hbm_frac": 12 * raw.numel() / (t[1] / 1e3) / (PEAK_HBM_GBS * 1e9),
            "single_scale_fp32_features_ms": tf32,
            "single_scale_fp32_features_voxels_per_s": raw.numel() / (tf32 / 1e3),
            "single_scale_fp32_features_hbm_frac": FEAT_BYTES_F32 * raw.numel() / (tf32 / 1e3) / (PEAK_HBM_GBS * 1e9),

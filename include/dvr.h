@@ -266,6 +266,19 @@ dvr_status dvr_render(const void *vol, int32_t vol_dtype, const dvr_grid *grid, 
                       const dvr_tf *tf, const dvr_render_params *rp, const dvr_camera *cams, int32_t ncam,
                       float *rgba, const dvr_ray_state *state, hipStream_t stream);
 
+/* Gather ceiling of dvr_render, for measurement (the bound on a raymarch with this access pattern,
+ * Sec. 2.4): walks the rays of dvr_render with the same arguments over the same samples, 0 .. k_last
+ * of each ray (k_last from that forward pass), with the same empty-brick skipping, and issues the
+ * same loads: the intensity corners of every sample, the TF segment test, and the feature corners of
+ * the samples with non-zero extinction.  Eq. 4, the exponential and the compositing are left out.
+ * k_last: device [ncam][H][W] int32 (dvr_ray_state.k_last of the forward pass); sink: device
+ * [ncam][H][W] float, overwritten with a per-ray sum of the fetched features (it only keeps the loads
+ * live); counters: device [2], 8-byte aligned, nullable, overwritten with the samples walked and
+ * those whose feature corners were fetched (equal to the forward pass's counters). */
+dvr_status dvr_render_gather(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_features_buf *feat,
+                             const dvr_tf *tf, const dvr_render_params *rp, const dvr_camera *cams, int32_t ncam,
+                             const int32_t *k_last, float *sink, uint64_t *counters, hipStream_t stream);
+
 /* Adjoint of dvr_render with respect to the TF values and the voxel intensities; the features
  * are held constant.  Each ray is walked back to front from the stored (T_last, k_last),
  * recomputing every sample exactly as the forward pass did.

@@ -17,7 +17,7 @@ import torch
 from . import _abi as abi
 from ._abi import DVRError
 
-__all__ = ["Features", "features", "render", "render_backward", "normalize", "DVRRender", "DVRError",
+__all__ = ["Features", "features", "render", "render_gather", "render_backward", "normalize", "DVRRender", "DVRError",
            "camera_struct", "lib", "Batch"]
 
 
@@ -211,6 +211,26 @@ def render(vol, feats: Features, knots, rgba, params, cams, want_state=True, out
     abi.check(lib().dvr_render(_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g), C.byref(fb),
                                C.byref(tf), C.byref(rp), carr, n, _ptr(img), C.byref(st) if st else None, _stream()))
     return img, T_last, k_last
+
+
+def render_gather(vol, feats: Features, knots, rgba, params, cams, k_last, sink=None, counters=None):
+    """dvr_render_gather (measurement): the loads of dvr_render over samples 0 .. k_last of each ray,
+    without the optics.  Returns the sink tensor [ncam][H][W] (a sum that keeps the loads live).
+    counters: optional int64 device tensor [2] overwritten with (walked, feature-fetching) samples."""
+    _require_cuda(vol)
+    carr = _cams(cams)
+    W, H = carr[0].width, carr[0].height
+    n = len(cams)
+    dev = feats.grad.device
+    sink = torch.empty((n, H, W), dtype=torch.float32, device=dev) if sink is None else sink
+    g = grid_struct(feats.shape, feats.spacing)
+    fb = feats.buf()
+    tf = _tf_struct(knots, rgba)
+    rp = _rparams(params)
+    abi.check(lib().dvr_render_gather(_ptr(vol), _dt(vol) if vol is not None else abi.DVR_F32, C.byref(g),
+                                      C.byref(fb), C.byref(tf), C.byref(rp), carr, n, _ptr(k_last), _ptr(sink),
+                                      _ptr(counters), _stream()))
+    return sink
 
 
 def render_backward(vol, feats: Features, knots, rgba, params, cams, T_last, k_last, dout, want_dvol=True,

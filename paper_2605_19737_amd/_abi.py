@@ -122,6 +122,8 @@ def load():
     L.dvr_features.argtypes = [vp, i32, P(Grid), P(FeatureParams), P(FeaturesBuf), vp, sz, vp]
     L.dvr_render.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32, vp,
                              P(RayState), vp]
+    L.dvr_render_gather.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32, vp,
+                                    vp, vp, vp]
     L.dvr_render_backward.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera), i32,
                                       P(RayState), vp, vp, vp, vp]
     L.dvr_render_backward_features.argtypes = [vp, i32, P(Grid), P(FeaturesBuf), P(TF), P(RenderParams), P(Camera),
@@ -134,7 +136,7 @@ def load():
     L.dvr_batch_destroy.argtypes = [vp]
     L.dvr_batch_autotune.argtypes = [P(BatchDesc), C.c_char_p, P(Tune)]
     for name in ("dvr_normalize_workspace", "dvr_normalize", "dvr_normalize_noalloc", "dvr_features_workspace", "dvr_bricks_count", "dvr_bricks_bytes", "dvr_histogram", "dvr_denoise_workspace", "dvr_denoise", "dvr_tissue_peaks", "dvr_tissue_tf", "dvr_features",
-                 "dvr_render", "dvr_render_backward", "dvr_render_backward_features", "dvr_features_backward_workspace",
+                 "dvr_render", "dvr_render_gather", "dvr_render_backward", "dvr_render_backward_features", "dvr_features_backward_workspace",
                  "dvr_features_backward", "dvr_batch_create", "dvr_batch_launch", "dvr_batch_check",
                  "dvr_batch_destroy", "dvr_batch_autotune"):
         getattr(L, name).restype = i32

@@ -536,6 +536,32 @@ dvr_status dvr_render(const void *vol, int32_t vol_dtype, const dvr_grid *grid, 
     return e == hipSuccess ? DVR_OK : dev_fail(e, "render launch");
 }
 
+dvr_status dvr_render_gather(const void *vol, int32_t vol_dtype, const dvr_grid *grid, const dvr_features_buf *feat,
+                             const dvr_tf *tf, const dvr_render_params *rp, const dvr_camera *cams, int32_t ncam,
+                             const int32_t *k_last, float *sink, uint64_t *counters, hipStream_t stream)
+{
+    if (ncam > 1 << 20) return fail(DVR_E_INVALID_ARG, "too many cameras");
+    dvr::KCam *kc = ncam > 0 ? new (std::nothrow) dvr::KCam[ncam] : nullptr;
+    if (ncam > 0 && !kc) return fail(DVR_E_NOMEM, "host allocation");
+    dvr::RenderArgs a;
+    dvr_status s = build_render_args(vol, vol_dtype, grid, feat, tf, rp, cams, ncam, a, kc);
+    if (s == DVR_OK && (!k_last || !sink)) s = fail(DVR_E_NULL, "k_last and sink are required");
+    if (s == DVR_OK && (((uintptr_t)k_last & 3u) || ((uintptr_t)sink & 3u) || ((uintptr_t)counters & 7u)))
+        s = fail(DVR_E_ALIGN, "k_last, sink or counters misaligned");
+    if (s != DVR_OK) {
+        delete[] kc;
+        return s;
+    }
+    a.launch.out = sink;
+    a.launch.k_last = const_cast<int32_t *>(k_last);
+    a.launch.counters = (unsigned long long *)counters;
+    hipError_t e = hipSuccess;
+    if (counters) e = dvr::launch_fill_zero((float *)counters, 4, stream);
+    if (e == hipSuccess) e = dvr::launch_render_gather(a, stream);
+    delete[] kc;
+    return e == hipSuccess ? DVR_OK : dev_fail(e, "render gather launch");
+}
+
 static dvr_status render_backward(const void *vol, int32_t vol_dtype, const dvr_grid *grid,
                                   const dvr_features_buf *feat, const dvr_tf *tf, const dvr_render_params *rp,
                                   const dvr_camera *cams, int32_t ncam, const dvr_ray_state *state,

@@ -141,5 +141,6 @@ hipError_t launch_denoise(const void *vol, int dt, const dvr_grid &g, int mode, 
 struct RenderArgs;
 hipError_t launch_render(const RenderArgs &a, hipStream_t st);
 hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st);
+hipError_t launch_render_gather(const RenderArgs &a, hipStream_t st);
 
 }  // namespace dvr

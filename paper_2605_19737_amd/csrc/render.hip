@@ -101,6 +101,30 @@ __global__ __launch_bounds__(256) void k_render(KFeat feat, KGrid g, KTF tf, KRe
     if (L.counters) count_samples<4>(L.counters, o.last, o.shaded);
 }
 
+// Gather ceiling of k_render (dvr_render_gather): the same rays, samples and loads, without the
+// optics; sink[pixel] keeps the loads live, counters count the samples walked and those whose
+// feature corners were fetched (equal to the forward pass's counts by construction).
+template <int LAYOUT, int DT, int KMAX>
+__global__ __launch_bounds__(256) void k_render_gather(KFeat feat, KGrid g, KTF tf, KRender rp, KLaunch L)
+{
+    __shared__ TFShared<KMAX> sh;
+    float kx[KMAX];
+    tf_load<KMAX>(sh, kx, tf);
+    __syncthreads();
+    uint32_t cam;
+    int pi, pj;
+    bool valid;
+    pixel_of(L, cam, pi, pj, valid);
+    const size_t pix = valid ? ((size_t)(L.cam_base + cam) * L.H + pj) * L.W + pi : 0;
+    const int kl = valid ? L.k_last[pix] : -1;
+    RayGeo r;
+    r.N = 0;
+    if (kl >= 0) r = ray_setup(load_cam(L, cam), pi, pj, g);
+    const RayOut o = march_fwd<LAYOUT, DT, KMAX, true>(feat, g, sh, kx, rp, 0.f, r, kl);
+    if (valid) L.out[pix] = o.C0;
+    if (L.counters) count_samples<4>(L.counters, o.last, o.shaded);
+}
+
 template <int LAYOUT, int DT, int KMAX, bool FG>
 __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf, KRender rp, KLaunch L)
 {
@@ -152,11 +176,16 @@ __global__ __launch_bounds__(256) void k_render_bwd(KFeat feat, KGrid g, KTF tf,
 }
 
 // ------------------------------------------------------------------------------------------------
+enum { kFwd = 0, kBwd = 1, kGather = 2 };
+
 template <int LAYOUT, int DT, int KMAX>
 static hipError_t launch_fwd_t(const KFeat &f, const KGrid &g, const KTF &tf, const KRender &rp, const KLaunch &L,
-                               uint32_t blocks, hipStream_t st, bool bwd)
+                               uint32_t blocks, hipStream_t st, int mode)
 {
-    if (bwd && L.dfeat)
+    const bool bwd = mode == kBwd;
+    if (mode == kGather)
+        hipLaunchKernelGGL((k_render_gather<LAYOUT, DT, KMAX>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
+    else if (bwd && L.dfeat)
         hipLaunchKernelGGL((k_render_bwd<LAYOUT, DT, KMAX, true>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
     else if (bwd)
         hipLaunchKernelGGL((k_render_bwd<LAYOUT, DT, KMAX, false>), dim3(blocks), dim3(256), 0, st, f, g, tf, rp, L);
@@ -167,14 +196,14 @@ static hipError_t launch_fwd_t(const KFeat &f, const KGrid &g, const KTF &tf, co
 
 template <int LAYOUT, int DT>
 static hipError_t launch_k(const KFeat &f, const KGrid &g, const KTF &tf, const KRender &rp, const KLaunch &L,
-                           uint32_t blocks, hipStream_t st, bool bwd)
+                           uint32_t blocks, hipStream_t st, int mode)
 {
-    if (tf.K <= 8) return launch_fwd_t<LAYOUT, DT, 8>(f, g, tf, rp, L, blocks, st, bwd);
-    if (tf.K <= 16) return launch_fwd_t<LAYOUT, DT, 16>(f, g, tf, rp, L, blocks, st, bwd);
-    return launch_fwd_t<LAYOUT, DT, 64>(f, g, tf, rp, L, blocks, st, bwd);
+    if (tf.K <= 8) return launch_fwd_t<LAYOUT, DT, 8>(f, g, tf, rp, L, blocks, st, mode);
+    if (tf.K <= 16) return launch_fwd_t<LAYOUT, DT, 16>(f, g, tf, rp, L, blocks, st, mode);
+    return launch_fwd_t<LAYOUT, DT, 64>(f, g, tf, rp, L, blocks, st, mode);
 }
 
-static hipError_t launch_any(const RenderArgs &a, hipStream_t st, bool bwd)
+static hipError_t launch_any(const RenderArgs &a, hipStream_t st, int mode)
 {
     for (int c0 = 0; c0 < a.ncam; c0 += kCamChunk) {
         KLaunch L = a.launch;
@@ -185,14 +214,14 @@ static hipError_t launch_any(const RenderArgs &a, hipStream_t st, bool bwd)
         const uint32_t blocks = (tiles + 7u) / 8u * 8u;
         hipError_t e;
         const int lay = a.feat.layout, dt = a.feat.dtype;
-        if (lay == DVR_PLANAR && dt == DVR_F32) e = launch_k<DVR_PLANAR, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_PLANAR && dt == DVR_F16) e = launch_k<DVR_PLANAR, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_INTERLEAVED && dt == DVR_F32) e = launch_k<DVR_INTERLEAVED, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_INTERLEAVED && dt == DVR_F16) e = launch_k<DVR_INTERLEAVED, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_SPLIT && dt == DVR_F32) e = launch_k<DVR_SPLIT, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_SPLIT && dt == DVR_F16) e = launch_k<DVR_SPLIT, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_QUAD && dt == DVR_F32) e = launch_k<DVR_QUAD, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
-        else if (lay == DVR_QUAD && dt == DVR_F16) e = launch_k<DVR_QUAD, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, bwd);
+        if (lay == DVR_PLANAR && dt == DVR_F32) e = launch_k<DVR_PLANAR, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_PLANAR && dt == DVR_F16) e = launch_k<DVR_PLANAR, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_INTERLEAVED && dt == DVR_F32) e = launch_k<DVR_INTERLEAVED, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_INTERLEAVED && dt == DVR_F16) e = launch_k<DVR_INTERLEAVED, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_SPLIT && dt == DVR_F32) e = launch_k<DVR_SPLIT, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_SPLIT && dt == DVR_F16) e = launch_k<DVR_SPLIT, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_QUAD && dt == DVR_F32) e = launch_k<DVR_QUAD, DVR_F32>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
+        else if (lay == DVR_QUAD && dt == DVR_F16) e = launch_k<DVR_QUAD, DVR_F16>(a.feat, a.grid, a.tf, a.rp, L, blocks, st, mode);
         else e = hipErrorInvalidValue;
         if (e != hipSuccess) return e;
     }
@@ -232,9 +261,17 @@ hipError_t launch_render(const RenderArgs &a, hipStream_t st)
         const hipError_t e = launch_brick_mask(a, st);
         if (e != hipSuccess) return e;
     }
-    return launch_any(a, st, false);
+    return launch_any(a, st, kFwd);
 }
-hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st) { return launch_any(a, st, true); }
+hipError_t launch_render_backward(const RenderArgs &a, hipStream_t st) { return launch_any(a, st, kBwd); }
+hipError_t launch_render_gather(const RenderArgs &a, hipStream_t st)
+{
+    if (a.feat.bricks) {
+        const hipError_t e = launch_brick_mask(a, st);
+        if (e != hipSuccess) return e;
+    }
+    return launch_any(a, st, kGather);
+}
 
 }  // namespace dvr
 

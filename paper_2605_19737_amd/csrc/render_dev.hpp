@@ -478,9 +478,15 @@ struct RayOut {
     int last, shaded;
 };
 
-template <int LAYOUT, int DT, int KMAX>
+// GATHER: the gather ceiling of this walk (a measurement, not the method).  The ray visits samples
+// 0 .. kl only (kl = the k_last of a forward pass with the same arguments) and issues the same loads
+// as the forward pass: the intensity corners of every non-skipped sample, the TF segment test, and
+// the feature corners where the extinction is non-zero; Eq. 4, the exponential and the compositing
+// are left out, and C0 returns a plain sum of the interpolated features that keeps the loads live.
+template <int LAYOUT, int DT, int KMAX, bool GATHER = false>
 __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, const TFShared<KMAX> &sh,
-                                            const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r)
+                                            const float (&kx)[KMAX], const KRender &rp, float invg, const RayGeo &r,
+                                            int kl = -1)
 {
     RayOut o_;
     // the opacity is accumulated as a sum of the positive terms T_k alpha_k, relatively accurate
@@ -508,7 +514,8 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
         float t_lo = INFINITY, t_hi = -INFINITY, t_x = 0.f;
         float4 t_v = make_float4(0.f, 0.f, 0.f, 0.f), t_s = t_v;
         bool t_below = false;
-        for (int k = 0; k < r.N; ++k) {
+        const int nk = GATHER ? min(r.N, kl + 1) : r.N;
+        for (int k = 0; k < nk; ++k) {
             if (skip) {
                 const int bi = ((int)(q[2] >> 34) * feat.nb[1] + (int)(q[1] >> 34)) * feat.nb[0] + (int)(q[0] >> 34);
                 if (bi != cur_brick) {
@@ -562,13 +569,17 @@ __device__ __forceinline__ RayOut march_fwd(const KFeat &feat, const KGrid &g, c
                 ch.g[2] = cc.interp(c, 3);
                 ch.k = cc.interp(c, 4);
                 ch.V = cc.interp(c, 5);
-                eq4(rp, invg, ch, dk, o);
-                const float ta = T * o.alpha;
-                C0 = fmaf(ta, o.c[0], C0);
-                C1 = fmaf(ta, o.c[1], C1);
-                C2 = fmaf(ta, o.c[2], C2);
-                A += ta;
-                T = T * o.om;
+                if constexpr (GATHER) {
+                    C0 += ((ch.g[0] + ch.g[1]) + (ch.g[2] + ch.k)) + (ch.V + o.tau);
+                } else {
+                    eq4(rp, invg, ch, dk, o);
+                    const float ta = T * o.alpha;
+                    C0 = fmaf(ta, o.c[0], C0);
+                    C1 = fmaf(ta, o.c[1], C1);
+                    C2 = fmaf(ta, o.c[2], C2);
+                    A += ta;
+                    T = T * o.om;
+                }
             }
             last = k;
             if (T <= rp.Tstop) break;
