@@ -33,6 +33,12 @@ import numpy as np
 
 SEED_BASE = 19737
 
+# Frangi's structure sensitivity of the benchmarked workloads, c = 1/2 max over voxels and scales of
+# |sigma^2 H|_F (Frangi's rule), computed once by the oracle (tests/golden/make_frangi_c.py writes
+# tests/golden/frangi_c.json) and fixed here, so the timed feature passes are single-pass.  The
+# batched set shares one value: half the largest norm over its 64 volumes.
+FRANGI_C = {"c2": 0.414322618, "c3": 0.137696885, "c4": 0.0771826, "c5": 0.151685491}
+
 # Tissue values of the simple phantom (background, CSF, GM, WM).
 C1_VALUES = (0.0, 0.2, 0.55, 0.8)
 # Semi-axes (x, y, z) in mm of the simple 64^3 phantom, outermost first.
@@ -318,7 +324,7 @@ def c2(width=1024, height=1024, views=None, nviews=360):
     knots, rgba = tf_head()
     views = range(nviews) if views is None else views
     cams = [persp_camera(dims, h, float(v), 15.0, width, height) for v in views]
-    return Workload("c2", vol, h, [1.0, 2.0, 3.0], c=0.25, tf_knots=knots, tf_rgba=rgba,
+    return Workload("c2", vol, h, [1.0, 2.0, 3.0], c=FRANGI_C["c2"], tf_knots=knots, tf_rgba=rgba,
                     params=render_params(lambda_g=0.5, lambda_v=2.0, et_alpha=0.99), cams=cams)
 
 
@@ -335,7 +341,7 @@ def c3(width=512, height=512, views=None):
     vol = _render_volume(dims[::-1], h, shells, centre, tubes, (), rng, ("gauss", 0.01)).astype(np.float32)
     views = range(8) if views is None else views
     cams = [ortho_camera(dims, h, 45.0 * k, 20.0, width, height) for k in views]
-    return Workload("c3", vol, h, [1.0], c=0.1, tf_knots=knots, tf_rgba=rgba,
+    return Workload("c3", vol, h, [1.0], c=FRANGI_C["c3"], tf_knots=knots, tf_rgba=rgba,
                     params=render_params(lambda_v=0.5, et_alpha=0.0), cams=cams,
                     extra=dict(target_tf_rgba=target_rgba))
 
@@ -357,7 +363,7 @@ def c4_volume(b, width=512, height=512, views=None):
     knots, rgba = tf_c1()
     views = range(4) if views is None else views
     cams = [ortho_camera(dims, h, 90.0 * k, 15.0, width, height) for k in views]
-    return Workload(f"c4_{b}", vol, h, [1.0], c=0.1, tf_knots=knots, tf_rgba=rgba,
+    return Workload(f"c4_{b}", vol, h, [1.0], c=FRANGI_C["c4"], tf_knots=knots, tf_rgba=rgba,
                     params=render_params(lambda_v=0.0, et_alpha=0.99), cams=cams)
 
 
@@ -393,7 +399,7 @@ def c5(width=2048, height=2048, views=None, dims=(512, 512, 400), spacing=(0.5, 
     del clean
     views = range(8) if views is None else views
     cams = [ortho_camera(dims, h, 45.0 * k, 20.0, width, height) for k in views]
-    return Workload("c5", raw, h, [0.5], c=0.25, tf_knots=knots, tf_rgba=rgba,
+    return Workload("c5", raw, h, [0.5], c=FRANGI_C["c5"], tf_knots=knots, tf_rgba=rgba,
                     params=render_params(lambda_g=0.5, lambda_v=2.0, et_alpha=0.99), cams=cams,
                     extra=dict(target_tf_rgba=target_rgba))
 
