@@ -172,9 +172,9 @@ __device__ __forceinline__ void frangi64_grad(const double l[3], double ia, doub
 }
 
 // order-preserving 64-bit key of (|g| rounded to FP32, lowest voxel index on a tie)
-__device__ __forceinline__ unsigned long long gkey(double gn, uint32_t v)
+__device__ __forceinline__ unsigned long long gkey(float gn, uint32_t v)
 {
-    return ((unsigned long long)__float_as_uint((float)gn) << 32) | (unsigned long long)(0xffffffffu - v);
+    return ((unsigned long long)__float_as_uint(gn) << 32) | (unsigned long long)(0xffffffffu - v);
 }
 
 template <int DT>
@@ -199,12 +199,17 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
     if (s == 0 && live) {
         const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
         const size_t row = (size_t)z * plane + (size_t)y * nx;
-        const double g0 = (ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)) - ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1))) * ih0;
-        const double g1 = (ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x) -
-                           ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x)) * ih1;
-        const double g2 = (ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x) -
-                           ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x)) * ih2;
+        const double ixp = ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)), ixm = ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1));
+        const double iyp = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x);
+        const double iym = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x);
+        const double izp = ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+        const double izm = ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+        const double g0 = (ixp - ixm) * ih0, g1 = (iyp - iym) * ih1, g2 = (izp - izm) * ih2;
         const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+        // the arg-max key takes |g| exactly as the feature pass rounds it: FP32 differences times the
+        // FP32 1/(2h), then grad_norm (the values |g|_max is the maximum of)
+        const float gn32 = grad_norm(((float)ixp - (float)ixm) * (float)ih0, ((float)iyp - (float)iym) * (float)ih1,
+                                     ((float)izp - (float)izm) * (float)ih2);
         double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
         const double dk = dfeat[3 * N + v];
         if (gg > 0.0 && dk != 0.0) {
@@ -229,7 +234,7 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
         dgt[v] = (float)d0;
         dgt[N + v] = (float)d1;
         dgt[2 * N + v] = (float)d2;
-        kv = gkey(sqrt(gg), v);
+        kv = gkey(gn32, v);
     }
     if (live && win[v] == (uint8_t)s) {
         const double dV = dfeat[4 * N + v];

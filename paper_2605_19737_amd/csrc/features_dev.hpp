@@ -107,7 +107,7 @@ __device__ __forceinline__ void eig_sym3(const float A[6], float &mu0, float &mu
     const float D = fmaf(M0, M0, fmaf(2.f, sB, 12.f * sC));
     const float J3 = b00 * fmaf(b11, b22, -b12 * b12) - b01 * fmaf(b01, b22, -b12 * b02) + b02 * fmaf(b01, b12, -b11 * b02);
     // 3 theta = atan2(y, x), y >= 0
-    const float y = sqrtf(D), x = 5.196152422706632f * J3;
+    const float y = __builtin_amdgcn_sqrtf(D), x = 5.196152422706632f * J3;
     const float ax = fabsf(x), lo = fminf(ax, y), hi = fmaxf(ax, y);
     float a = hi > 0.f ? atan01(lo * __builtin_amdgcn_rcpf(hi)) : 0.f;
     if (y > ax) a = 1.5707963267948966f - a;
@@ -124,7 +124,7 @@ __device__ __forceinline__ void eig_sym3(const float A[6], float &mu0, float &mu
     cs = fmaf(cs, v, 0.04166639f);
     cs = fmaf(cs, v, -0.49999997f);
     cs = fmaf(cs, v, 1.f);
-    const float p = sc * sqrtf(J2 * (1.f / 3.f));
+    const float p = sc * __builtin_amdgcn_sqrtf(J2 * (1.f / 3.f));
     mu2 = fmaf(2.f * p, cs, m);
     const float ps = 1.7320508075688772f * p * sn, pc = p * cs;
     mu0 = m - (pc + ps);
@@ -163,6 +163,35 @@ __device__ __forceinline__ void eig_jacobi64(const float A[6], float &mu0, float
     mu0 = (float)lo;
     mu1 = (float)(d[0] + d[1] + d[2] - lo - hi);
     mu2 = (float)hi;
+}
+
+// |g| as the feature pass takes it (|g|_max is the largest of these; the adjoint finds its voxel with
+// the same expression).  The square roots of this file are the hardware's (within 1 ulp).
+__device__ __forceinline__ float grad_norm(float gx, float gy, float gz)
+{
+    return __builtin_amdgcn_sqrtf(gx * gx + gy * gy + gz * gz);
+}
+
+// Whether V can be non-zero at A = sigma^2 H.  With eigenvalues mu0 <= mu1 <= mu2, V != 0 exactly when
+// mu1 + mu2 < 0 (that implies mu1 < 0), i.e. when tr(A) I - A, whose eigenvalues are the pair sums
+// mu_i + mu_j, is negative definite: M = A - tr(A) I positive definite.  By Sylvester's criterion a
+// positive definite M has positive leading principal minors m00, m00 m11 - m01^2 and det M, so a
+// minor below minus a margin proves V = 0.  The margins (1e-4 s^k for the minor of order k, s the
+// largest |m_ij|) are ~100 times the rounding of the minors and put mu1 + mu2 at >= 1e-5 s, far
+// above the eigen-solve's error, so every voxel left out would also get V = 0 from its eigenvalues;
+// the rest (about half of the voxels with tr(A) < 0) take the eigen-solve.
+__device__ __forceinline__ bool maybe_vessel(const float A[6])
+{
+    const float t = A[0] + A[1] + A[2];
+    if (!(t < 0.f)) return false;
+    const float m00 = A[0] - t, m11 = A[1] - t, m22 = A[2] - t, m01 = A[3], m02 = A[4], m12 = A[5];
+    const float s = fmaxf(fmaxf(fmaxf(fabsf(m00), fabsf(m11)), fmaxf(fabsf(m22), fabsf(m01))),
+                          fmaxf(fabsf(m02), fabsf(m12)));
+    const float e = 1e-4f * s, e2 = e * s, e3 = e2 * s;
+    const float d2 = fmaf(m00, m11, -m01 * m01);
+    const float c0 = fmaf(m11, m22, -m12 * m12), c1 = fmaf(m01, m22, -m12 * m02), c2 = fmaf(m01, m12, -m11 * m02);
+    const float d3 = fmaf(m00, c0, fmaf(-m01, c1, m02 * c2));
+    return !(m00 < -e || d2 < -e2 || d3 < -e3);
 }
 
 // 1 - exp(-x) for x >= 0 with a relative error of a few ulps: a series below 1/16, else the
@@ -373,8 +402,8 @@ struct Compact {
 // intensities In = (I, I[x+1], I[x-1], I[y+1], I[y-1], I[z+1], I[z-1]) (clamped neighbours): the
 // gradient (Eq. 2), k (Eq. 3), the eigenvalues of sigma^2 H and V.  Updates vmax with |g| (first
 // scale) or |sigma^2 H|_F (Frangi-c pass).
-// V can be non-zero only where tr(sigma^2 H) < 0 (it needs the two eigenvalues of largest magnitude
-// negative), so only those voxels take the eigen-solve and Frangi: the workgroup writes them to one
+// V can be non-zero only where maybe_vessel holds (a test on sigma^2 H that is exact up to a rounding
+// margin), so only those voxels take the eigen-solve and Frangi: the workgroup writes them to one
 // list in the LDS area cw (Compact<NV>::kFloats floats), solves the list densely, one voxel per
 // lane, and reads the results back.  Elsewhere V = 0 exactly, as the full evaluation would give.
 // Every thread of the workgroup must call it (it holds barriers).
@@ -403,7 +432,7 @@ __device__ __forceinline__ void voxels_out(const XYArgs &a, float sigma2, const 
         for (int i = 0; i < NV; ++i) {
             const float f2 = A[i][0] * A[i][0] + A[i][1] * A[i][1] + A[i][2] * A[i][2] +
                              2.f * (A[i][3] * A[i][3] + A[i][4] * A[i][4] + A[i][5] * A[i][5]);
-            if (live[i]) vmax = fmaxf(vmax, sqrtf(f2));
+            if (live[i]) vmax = fmaxf(vmax, __builtin_amdgcn_sqrtf(f2));
         }
         return;
     }
@@ -416,7 +445,7 @@ __device__ __forceinline__ void voxels_out(const XYArgs &a, float sigma2, const 
     int wcount = 0;
 #pragma unroll
     for (int i = 0; i < NV; ++i) {
-        need[i] = live[i] && (A[i][0] + A[i][1] + A[i][2] < 0.f);
+        need[i] = live[i] && maybe_vessel(A[i]);
         const uint64_t m = __ballot(need[i]);
         slot[i] = wcount + (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(m >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)m, 0u));
         wcount += __popcll(m);
@@ -449,7 +478,7 @@ __device__ __forceinline__ void voxels_out(const XYArgs &a, float sigma2, const 
         gx_ = (In[i][1] - In[i][2]) * a.inv2h[0];
         gy_ = (In[i][3] - In[i][4]) * a.inv2h[1];
         gz_ = (In[i][5] - In[i][6]) * a.inv2h[2];
-        vmax = fmaxf(vmax, sqrtf(gx_ * gx_ + gy_ * gy_ + gz_ * gz_));
+        vmax = fmaxf(vmax, grad_norm(gx_, gy_, gz_));
         const float gm = fmaxf(fabsf(gx_), fmaxf(fabsf(gy_), fabsf(gz_)));
         if (gm > 0.f) {
             const float ig = __builtin_amdgcn_rcpf(gm);
