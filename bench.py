@@ -81,6 +81,9 @@ def main():
     ap.add_argument("--only-adjoint", action="store_true",
                     help="just the render adjoint of 8 head views (every 45th) after one forward, without and then "
                          "with the feature gradients (for profiling)")
+    ap.add_argument("--only-features", action="store_true",
+                    help="just the feature passes, for profiling: the head's 3 scales (quad layout) 4 times, then "
+                         "the 512x512x400 volume's single scale in FP32 planar 4 times")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -123,6 +126,26 @@ def main():
     img = torch.empty((V, 1024, 1024, 4), dtype=torch.float32, device=dev)
     counters = torch.zeros(2, dtype=torch.int64, device=dev)
     stream = torch.cuda.current_stream()
+
+    if args.only_features:
+        for _ in range(4):
+            dvr.features(vol, w.spacing, w.sigmas, c=w.c, layout=feats.layout, out=feats, ws=ws)
+        torch.cuda.synchronize()
+        del feats, ws, img
+        w5 = phantoms.c5(8, 8, views=[0])
+        raw = torch.from_numpy(w5.vol.view(np.int16)).to(dev)
+        v32 = dvr.normalize(raw, torch.float32)
+        f32 = dvr.alloc_features(tuple(raw.shape), w5.spacing, torch.float32, abi_.DVR_PLANAR, bricks=False)
+        ws32 = torch.empty(dvr.features_workspace_bytes(tuple(raw.shape), w5.spacing, w5.sigmas, c=w5.c),
+                           dtype=torch.uint8, device=dev)
+        for _ in range(4):
+            dvr.features(v32, w5.spacing, w5.sigmas, c=w5.c, eig_gap=1e-3, layout=abi_.DVR_PLANAR, out=f32, ws=ws32)
+        if args.copy_calibration:
+            src = torch.empty(1 << 28, dtype=torch.float32, device=dev).fill_(1.0)
+            torch.empty_like(src).copy_(src)
+        torch.cuda.synchronize()
+        log("feature passes done (head x4, 512x512x400 single scale x4)")
+        return
 
     if args.only_adjoint:
         dvr.features(vol, w.spacing, w.sigmas, c=w.c, layout=feats.layout, out=feats, ws=ws)
