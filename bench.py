@@ -479,7 +479,9 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     # split layout on both sides of the comparison (on these small thick-slice volumes the quad layout's
     # extra quad-building step costs the batched launch more than its two-load corners save: 85.8 vs 83.1 ms)
     lay = abi_b.DVR_SPLIT
-    feats = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
+    # no brick tables on either side: on these volumes the per-call raymarch ran 84.8 ms with them and
+    # 82.0 ms without (the lookups cost more than the transparent samples they skip)
+    feats = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay, bricks=False) for v, sp in zip(vols, sps)]
     views = []
     for i, w in enumerate(ws):
         for cam in w.cams:
@@ -506,7 +508,7 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     # the same work as per-call launches (features per volume, then 4 views per volume), with counters
     cnt = torch.zeros(2, dtype=torch.int64, device=dev)
     total = 0
-    pf = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay) for v, sp in zip(vols, sps)]
+    pf = [dvr.alloc_features(tuple(v.shape), sp, torch.float32, lay, bricks=False) for v, sp in zip(vols, sps)]
     wsp = [torch.empty(dvr.features_workspace_bytes(tuple(v.shape), sp, ws[0].sigmas, c=ws[0].c), dtype=torch.uint8,
                        device=dev) for v, sp in zip(vols, sps)]
     imgs = [torch.empty((4, 512, 512, 4), dtype=torch.float32, device=dev) for _ in vols]
@@ -529,7 +531,9 @@ def leg_batch(dev, stream, dvr, torch, np, log, nvol=64):
     t_calls = e0.elapsed_time(e1) / 1e3
     out = {"volumes": nvol, "voxels": nvox, "views": len(views), "image": [512, 512], "tune": tune,
            "graph_launch_ms": 1e3 * t_batch, "samples_evaluated": total, "samples_per_s": total / t_batch,
-           "per_call_ms": 1e3 * t_calls, "per_call_samples_per_s": total / t_calls}
+           "per_call_ms": 1e3 * t_calls, "per_call_samples_per_s": total / t_calls,
+           "graph_speedup": t_calls / t_batch,
+           "like_for_like": "both sides: split FP32 features, no brick tables, the same TF, sigma and views"}
     log(f"batched: {1e3 * t_batch:.2f} ms per graph launch ({total / t_batch:.4g} samples/s) vs per-call "
         f"{1e3 * t_calls:.2f} ms ({total / t_calls:.4g} samples/s); tune {tune}")
     return out

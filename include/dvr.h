@@ -391,8 +391,10 @@ dvr_status dvr_batch_launch(dvr_batch *plan, hipStream_t stream);
 /* Waits for stream and reports DVR_E_TIMEOUT if a dependency wait of the last launch expired. */
 dvr_status dvr_batch_check(dvr_batch *plan, hipStream_t stream);
 dvr_status dvr_batch_destroy(dvr_batch *plan);
-/* Picks the tile shapes: times each candidate dvr_tune on this batch (graph replays, HIP events)
- * and returns the fastest.  With cache_path, results are kept in a JSON file keyed by the batch's
+/* Picks the tile shapes: times candidate dvr_tune values on this batch (graph replays, HIP events) by
+ * coordinate descent from the defaults (two sweeps over wg_per_cu 2, 3, 4, 6, 8; xy_tile 0-2; xy_zrun
+ * 8, 16, 32; z_chunk 4, 8, 16, 32; ray_tile 0-2, each field with the others at the best so far) and
+ * returns the fastest.  With cache_path, results are kept in a JSON file keyed by the batch's
  * shape class and reused.  Synchronous; overwrites the batch's outputs. */
 dvr_status dvr_batch_autotune(const dvr_batch_desc *desc, const char *cache_path, dvr_tune *best);
 

@@ -171,6 +171,20 @@ __device__ __forceinline__ void quads_slab(const T *__restrict__ src, T4 *__rest
     }
 }
 
+// The fixed-radius tile for radius Rr (a uniform value) over slices [z0, z1), if 2 <= Rr <= 10.
+template <int DT, int LAYOUT, int TX, int TY, int R, typename ST>
+__device__ __forceinline__ bool xy_fixed(const XYArgs &a, const ST &taps, int Rr, int x0, int y0, int z0, int z1,
+                                         float *lds, float &vmax)
+{
+    if constexpr (R > 10) {
+        return false;
+    } else {
+        if (Rr != R) return xy_fixed<DT, LAYOUT, TX, TY, R + 1>(a, taps, Rr, x0, y0, z0, z1, lds, vmax);
+        vmax = xy_run_r<DT, DT, LAYOUT, R, TX, TY>(a, taps, x0, y0, z0, z1, lds, lds + XYTileR<R, TX, TY>::NF);
+        return true;
+    }
+}
+
 template <int LAYOUT, int DT, int KMAX, int TXY>
 __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
 {
@@ -242,8 +256,15 @@ __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
             const int bx = w.a % V.tiles_x, by = w.a / V.tiles_x;
             const int z1 = min(w.b + A.zrun, V.n[2]);
             float vmax = 0.f;
-            for (int z = w.b; z < z1; ++z)
-                vmax = fmaxf(vmax, xy_tile<DT, DT, FLAYOUT, TX, TY>(a, taps, bx * TX, by * TY, z, lds));
+            // the fixed-radius tile (equal x and y radius 2..10) for the split-layout features of the
+            // split and quad launches; the generic tile otherwise
+            bool done = false;
+            if constexpr (TXY == 0 && FLAYOUT == DVR_SPLIT)
+                if (taps.ax[0].R == taps.ax[1].R)
+                    done = xy_fixed<DT, FLAYOUT, TX, TY, 2>(a, taps, taps.ax[0].R, bx * TX, by * TY, w.b, z1, lds, vmax);
+            if (!done)
+                for (int z = w.b; z < z1; ++z)
+                    vmax = fmaxf(vmax, xy_tile<DT, DT, FLAYOUT, TX, TY>(a, taps, bx * TX, by * TY, z, lds));
             if (s == 0) {
                 vmax = wave_max(vmax);
                 if ((threadIdx.x & 63) == 0) atomic_max_pos(V.gmax, vmax);
@@ -394,7 +415,9 @@ static dvr_tune default_tune()
     dvr_tune t;
     t.wg_per_cu = 4;
     t.xy_tile = 0;
-    t.xy_zrun = 4;
+    // long z runs: every item ends with a device-scope release, which writes the XCD's L2 back; 32
+    // slices per item took the 64-volume feature phase from 27.8 to 12.0 ms (4 slices per item)
+    t.xy_zrun = 32;
     t.z_chunk = 8;
     t.ray_tile = 0;
     return t;
@@ -731,40 +754,19 @@ extern "C" dvr_status dvr_batch_autotune(const dvr_batch_desc *desc, const char 
             return DVR_OK;
         }
     }
-    std::vector<dvr_tune> cand;
-    for (int wg : {2, 4, 8})
-        for (int xt : {0, 1, 2})
-            for (int rt : {0, 1, 2}) {
-                dvr_tune t = default_tune();
-                t.wg_per_cu = wg;
-                t.xy_tile = xt;
-                t.ray_tile = rt;
-                cand.push_back(t);
-            }
-    for (int zr : {1, 8}) {
-        dvr_tune t = default_tune();
-        t.xy_zrun = zr;
-        cand.push_back(t);
-    }
-    for (int zc : {2, 32}) {
-        dvr_tune t = default_tune();
-        t.z_chunk = zc;
-        cand.push_back(t);
-    }
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
         return fail(DVR_E_DEVICE, "event creation");
-    float best_ms = INFINITY;
-    dvr_tune best_t = default_tune();
     dvr_status last = DVR_OK;
-    for (const dvr_tune &t : cand) {
+    // one candidate: build the plan, one warm replay, then two timed replays
+    auto time_tune = [&](const dvr_tune &t) -> float {
         dvr_batch_desc d = *desc;
         d.tune = &t;
         dvr_batch *p = nullptr;
         dvr_status s = dvr_batch_create(&d, &p);
         if (s != DVR_OK) {
             last = s;
-            continue;  // e.g. a tile whose halo does not fit in LDS
+            return INFINITY;  // e.g. a tile whose halo does not fit in LDS
         }
         float ms = INFINITY;
         if (dvr_batch_launch(p, p->stream) == DVR_OK && dvr_batch_check(p, p->stream) == DVR_OK) {
@@ -778,11 +780,36 @@ extern "C" dvr_status dvr_batch_autotune(const dvr_batch_desc *desc, const char 
             }
         }
         dvr_batch_destroy(p);
-        if (ms < best_ms) {
-            best_ms = ms;
-            best_t = t;
-        }
-    }
+        return ms;
+    };
+    // coordinate descent from the defaults, two sweeps: each field in turn over its candidate values
+    // with the others at the best so far (the fields interact weakly: the feature items use xy_tile,
+    // xy_zrun and z_chunk, the ray items ray_tile, and wg_per_cu sets the occupancy of both)
+    const std::vector<int> vals[5] = {{2, 3, 4, 6, 8}, {0, 1, 2}, {8, 16, 32}, {4, 8, 16, 32}, {0, 1, 2}};
+    auto field = [](dvr_tune &t, int f) -> int & {
+        return f == 0 ? t.wg_per_cu : (f == 1 ? t.xy_tile : (f == 2 ? t.xy_zrun : (f == 3 ? t.z_chunk : t.ray_tile)));
+    };
+    std::map<std::vector<int>, float> seen;
+    auto key_of = [](const dvr_tune &t) {
+        return std::vector<int>{t.wg_per_cu, t.xy_tile, t.xy_zrun, t.z_chunk, t.ray_tile};
+    };
+    dvr_tune best_t = default_tune();
+    float best_ms = time_tune(best_t);
+    seen[key_of(best_t)] = best_ms;
+    for (int sweep = 0; sweep < 2; ++sweep)
+        for (int f = 0; f < 5; ++f)
+            for (int v : vals[f]) {
+                dvr_tune t = best_t;
+                field(t, f) = v;
+                const auto k = key_of(t);
+                if (seen.count(k)) continue;
+                const float ms = time_tune(t);
+                seen[k] = ms;
+                if (ms < best_ms) {
+                    best_ms = ms;
+                    best_t = t;
+                }
+            }
     hipEventDestroy(e0);
     hipEventDestroy(e1);
     if (!isfinite(best_ms)) return last != DVR_OK ? last : fail(DVR_E_DEVICE, "no candidate tune ran");

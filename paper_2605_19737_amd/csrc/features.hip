@@ -106,35 +106,17 @@ __global__ __launch_bounds__(NT) void k_xypass_r(XYArgs a, ScaleTaps taps)
     using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY>;
     __shared__ float F[T::NF];
     __shared__ float Fy[T::NFY];
-    S s(a, taps, F, Fy, blockIdx.x * TX, blockIdx.y * TY);
-    float vmax = 0.f;
+    float vmax;
     if constexpr (kZRun == 1) {
+        S s(a, taps, F, Fy, blockIdx.x * TX, blockIdx.y * TY);
         const int z = blockIdx.z;
         s.load(z);
         s.store();
         __syncthreads();
         vmax = s.compute(z, s.In, s.Vp);
-        if (a.fro_pass || a.first) {
-            vmax = wave_max(vmax);
-            if ((threadIdx.x & 63) == 0) atomic_max_pos(a.fro_pass ? a.fro : a.gmax, vmax);
-        }
-        return;
-    }
-    const int z0 = blockIdx.z * kZRun, z1 = min(z0 + kZRun, a.nz);
-    s.load(z0);
-    for (int z = z0; z < z1; ++z) {
-        __syncthreads();  // the previous slice's readers of F (its y filters, its compaction lists) are done
-        s.store();
-        float Ic[S::NV][7], Vc[S::NV];
-#pragma unroll
-        for (int i = 0; i < S::NV; ++i) {
-            Vc[i] = s.Vp[i];
-#pragma unroll
-            for (int k = 0; k < 7; ++k) Ic[i][k] = s.In[i][k];
-        }
-        if (z + 1 < z1) s.load(z + 1);
-        __syncthreads();
-        vmax = fmaxf(vmax, s.compute(z, Ic, Vc));
+    } else {
+        const int z0 = blockIdx.z * kZRun, z1 = min(z0 + kZRun, a.nz);
+        vmax = xy_run_r<DT, OUT_DT, LAYOUT, R, TX, TY>(a, taps, blockIdx.x * TX, blockIdx.y * TY, z0, z1, F, Fy);
     }
     if (a.fro_pass || a.first) {
         vmax = wave_max(vmax);

@@ -660,8 +660,8 @@ __device__ __forceinline__ float xy_tile(const XYArgs &a, const ST &taps, int x0
 // Fixed-radius filters: the same sums as filt3 / filtG / filtD1 / filtD2 with the stencil radius R a
 // compile-time constant, so the loops unroll and the taps are read at constant offsets.  The
 // smoothing tap G[R] is exactly zero (R = r + 1), so its term is left out.
-template <int R, typename F>
-__device__ __forceinline__ float rG(const AxisTaps &t, F &&v)
+template <int R, typename AT, typename F>
+__device__ __forceinline__ float rG(const AT &t, F &&v)
 {
     float g = t.G[0] * v(0);
 #pragma unroll
@@ -669,8 +669,8 @@ __device__ __forceinline__ float rG(const AxisTaps &t, F &&v)
     return g;
 }
 
-template <int R, typename F>
-__device__ __forceinline__ float rD1(const AxisTaps &t, int cls, F &&v)
+template <int R, typename AT, typename F>
+__device__ __forceinline__ float rD1(const AT &t, int cls, F &&v)
 {
     float d = 0.f;
     if (cls == 0) {
@@ -686,8 +686,8 @@ __device__ __forceinline__ float rD1(const AxisTaps &t, int cls, F &&v)
     return d;
 }
 
-template <int R, typename F>
-__device__ __forceinline__ float rD2(const AxisTaps &t, int cls, F &&v)
+template <int R, typename AT, typename F>
+__device__ __forceinline__ float rD2(const AT &t, int cls, F &&v)
 {
     float d;
     if (cls == 0) {
@@ -706,8 +706,8 @@ __device__ __forceinline__ float rD2(const AxisTaps &t, int cls, F &&v)
     return d;
 }
 
-template <int R, typename F>
-__device__ __forceinline__ Line3 r3(const AxisTaps &t, int cls, F &&v)
+template <int R, typename AT, typename F>
+__device__ __forceinline__ Line3 r3(const AT &t, int cls, F &&v)
 {
     Line3 o;
     if (cls == 0) {
@@ -750,7 +750,7 @@ struct XYTileR {
 // One 64 x TY tile of the fixed-radius pass, for a run of z slices: the loads of a slice (its staged
 // z-filtered fields with halo, the intensities of the gradient and, after the first scale, the V so
 // far) are issued into registers while the previous slice is computed.
-template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY>
+template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST = ScaleTaps>
 struct XYSlab {
     using T = XYTileR<R, TX, TY>;
     static constexpr int W = T::W, HH = T::HH;
@@ -761,7 +761,7 @@ struct XYSlab {
     static constexpr int RPW = (NROW + NW - 1) / NW;
 
     const XYArgs &a;
-    const ScaleTaps &taps;
+    const ST &taps;
     float *F, *Fy;
     int x0, y0, nx, ny, nz;
     uint32_t plane, N;
@@ -772,7 +772,7 @@ struct XYSlab {
     float In[NV][7];
     float Vp[NV];
 
-    __device__ __forceinline__ XYSlab(const XYArgs &a_, const ScaleTaps &t_, float *F_, float *Fy_, int x0_, int y0_)
+    __device__ __forceinline__ XYSlab(const XYArgs &a_, const ST &t_, float *F_, float *Fy_, int x0_, int y0_)
         : a(a_), taps(t_), F(F_), Fy(Fy_), x0(x0_), y0(y0_)
     {
         nx = a.nx;
@@ -860,8 +860,8 @@ struct XYSlab {
     // and earlier V (In, Vp: copies taken before the next slice's loads were issued)
     __device__ __forceinline__ float compute(int z, const float (&Ic)[NV][7], const float (&Vc)[NV])
     {
-        const AxisTaps &tx = taps.ax[0];
-        const AxisTaps &ty = taps.ax[1];
+        const auto &tx = taps.ax[0];
+        const auto &ty = taps.ax[1];
         const int t = threadIdx.x;
         // y filters: all TY rows x W columns of the tile; interior sums everywhere, then the one-sided
         // forms on the first and last row of the volume
@@ -959,6 +959,35 @@ struct XYSlab {
         return vmax;
     }
 };
+
+// The fixed-radius tile over slices [z0, z1), each slice's loads issued while the previous slice is
+// computed.  F, Fy: XYTileR<R, TX, TY>::NF and ::NFY floats of LDS.  Returns this lane's contribution
+// to |g|_max (first scale) or max |sigma^2 H|_F (Frangi-c pass).  Every thread of the workgroup must
+// call it; it starts with a barrier, so the LDS may still be in use by an earlier tile.
+template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST>
+__device__ __forceinline__ float xy_run_r(const XYArgs &a, const ST &taps, int x0, int y0, int z0, int z1, float *F,
+                                          float *Fy)
+{
+    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY, ST>;
+    S s(a, taps, F, Fy, x0, y0);
+    float vmax = 0.f;
+    s.load(z0);
+    for (int z = z0; z < z1; ++z) {
+        __syncthreads();  // the previous slice's readers of F (its y filters, its compaction lists) are done
+        s.store();
+        float Ic[S::NV][7], Vc[S::NV];
+#pragma unroll
+        for (int i = 0; i < S::NV; ++i) {
+            Vc[i] = s.Vp[i];
+#pragma unroll
+            for (int k = 0; k < 7; ++k) Ic[i][k] = s.In[i][k];
+        }
+        if (z + 1 < z1) s.load(z + 1);
+        __syncthreads();
+        vmax = fmaxf(vmax, s.compute(z, Ic, Vc));
+    }
+    return vmax;
+}
 
 // LDS floats of the generic tile: the staged fields (whose space the four waves' compaction lists
 // reuse after the y filters) and the y-filtered fields
