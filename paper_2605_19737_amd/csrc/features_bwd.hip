@@ -83,6 +83,22 @@ __device__ __forceinline__ double frangi64(double l1, double l2, double l3, doub
     return -expm1(-Ra2 * ia) * exp(-Rb2 * ib) * -expm1(-S2 * ic);
 }
 
+// Whether V can be non-zero at A (FP64): V != 0 exactly when A - tr(A) I is positive definite (its
+// eigenvalues are minus the pair sums of A's), so a leading principal minor of it below minus a
+// margin proves V = 0 (Sylvester's criterion).  Margins of 1e-5 s^k (s the largest |m_ij|) put the
+// pair sum at >= 1e-6 s, far above the error of the FP64 closed-form eigenvalues.
+__device__ __forceinline__ bool maybe_vessel64(const double A[6])
+{
+    const double t = A[0] + A[1] + A[2];
+    if (!(t < 0.0)) return false;
+    const double m00 = A[0] - t, m11 = A[1] - t, m22 = A[2] - t, m01 = A[3], m02 = A[4], m12 = A[5];
+    const double sc = fmax(fmax(fmax(fabs(m00), fabs(m11)), fmax(fabs(m22), fabs(m01))), fmax(fabs(m02), fabs(m12)));
+    const double e = 1e-5 * sc, e2 = e * sc, e3 = e2 * sc;
+    const double d2 = m00 * m11 - m01 * m01;
+    const double d3 = m00 * (m11 * m22 - m12 * m12) - m01 * (m01 * m22 - m12 * m02) + m02 * (m01 * m12 - m11 * m02);
+    return !(m00 < -e || d2 < -e2 || d3 < -e3);
+}
+
 // winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0
 __global__ __launch_bounds__(256) void k_fb_win(const float *__restrict__ H, double *__restrict__ best,
                                                 uint8_t *__restrict__ win, int s, double sigma2, double ia, double ib,
@@ -93,13 +109,16 @@ __global__ __launch_bounds__(256) void k_fb_win(const float *__restrict__ H, dou
     double A[6];
 #pragma unroll
     for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
-    double lo, mi, hi;
-    eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
-    double a = lo, b = mi, c = hi, t;
-    if (key_less(b, a)) { t = a; a = b; b = t; }
-    if (key_less(c, b)) { t = b; b = c; c = t; }
-    if (key_less(b, a)) { t = a; a = b; b = t; }
-    const double V = frangi64(a, b, c, ia, ib, ic);
+    double V = 0.0;
+    if (maybe_vessel64(A)) {
+        double lo, mi, hi;
+        eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
+        double a = lo, b = mi, c = hi, t;
+        if (key_less(b, a)) { t = a; a = b; b = t; }
+        if (key_less(c, b)) { t = b; b = c; c = t; }
+        if (key_less(b, a)) { t = a; a = b; b = t; }
+        V = frangi64(a, b, c, ia, ib, ic);
+    }
     const double prev = s == 0 ? 0.0 : best[v];
     if (s == 0) win[v] = 255;
     if (V > prev) {
@@ -236,40 +255,68 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
         dgt[2 * N + v] = (float)d2;
         kv = gkey(gn32, v);
     }
-    if (live && win[v] == (uint8_t)s) {
-        const double dV = dfeat[4 * N + v];
-        if (dV != 0.0) {
-            double A[6], lam[3], Q[3][3];
+    // the vesselness term: voxels whose winning scale is s and whose dL/dV is not 0, compacted over the
+    // workgroup (a few per cent of the voxels; left in place, every wave would run the Jacobi
+    // iteration for its few such lanes) and solved densely, one per lane
+    __shared__ float cH[7][256];      // sigma^2 H (6 entries) and dL/dV of the listed voxels
+    __shared__ double cP[6][256];     // their dL/dH
+    __shared__ int ccount[4];
+    const bool need = live && win[v] == (uint8_t)s && dfeat[4 * N + v] != 0.f;
+    const uint64_t bal = __ballot(need);
+    const int wv = threadIdx.x >> 6;
+    int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if ((threadIdx.x & 63) == 0) ccount[wv] = __popcll(bal);
+    __syncthreads();
+    int count = 0;
 #pragma unroll
-            for (int k = 0; k < 6; ++k) A[k] = sigma2 * Hd[k];
-            jacobi3v(A, lam, Q);
-            int o[3] = {0, 1, 2}, t;
-            if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
-            if (key_less(lam[o[2]], lam[o[1]])) { t = o[1]; o[1] = o[2]; o[2] = t; }
-            if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
-            const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
-            double f[3];
-            frangi64_grad(ls, ia, ib, ic, f);
-            // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice)
-            double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    for (int w = 0; w < 4; ++w) {
+        slot += (w < wv) ? ccount[w] : 0;
+        count += ccount[w];
+    }
+    if (need) {
 #pragma unroll
-            for (int i = 0; i < 3; ++i) {
-                const double x0 = Q[0][o[i]], x1 = Q[1][o[i]], x2 = Q[2][o[i]];
-                P[0] += f[i] * x0 * x0;
-                P[1] += f[i] * x1 * x1;
-                P[2] += f[i] * x2 * x2;
-                P[3] += f[i] * x0 * x1;
-                P[4] += f[i] * x0 * x2;
-                P[5] += f[i] * x1 * x2;
-            }
-            const double w = dV * sigma2;
-            hb[0] += w * P[0];
-            hb[1] += w * P[1];
-            hb[2] += w * P[2];
-            hb[3] += 2.0 * w * P[3];
-            hb[4] += 2.0 * w * P[4];
-            hb[5] += 2.0 * w * P[5];
+        for (int k = 0; k < 6; ++k) cH[k][slot] = (float)Hd[k];
+        cH[6][slot] = dfeat[4 * N + v];
+    }
+    __syncthreads();
+    if ((int)threadIdx.x < count) {
+        const int q = threadIdx.x;
+        double A[6], lam[3], Q[3][3];
+#pragma unroll
+        for (int k = 0; k < 6; ++k) A[k] = sigma2 * (double)cH[k][q];
+        const double dV = cH[6][q];
+        jacobi3v(A, lam, Q);
+        int o[3] = {0, 1, 2}, t;
+        if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+        if (key_less(lam[o[2]], lam[o[1]])) { t = o[1]; o[1] = o[2]; o[2] = t; }
+        if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+        const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
+        double f[3];
+        frangi64_grad(ls, ia, ib, ic, f);
+        // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice)
+        double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+        for (int i = 0; i < 3; ++i) {
+            const double x0 = Q[0][o[i]], x1 = Q[1][o[i]], x2 = Q[2][o[i]];
+            P[0] += f[i] * x0 * x0;
+            P[1] += f[i] * x1 * x1;
+            P[2] += f[i] * x2 * x2;
+            P[3] += f[i] * x0 * x1;
+            P[4] += f[i] * x0 * x2;
+            P[5] += f[i] * x1 * x2;
         }
+        const double w = dV * sigma2;
+        cP[0][q] = w * P[0];
+        cP[1][q] = w * P[1];
+        cP[2][q] = w * P[2];
+        cP[3][q] = 2.0 * w * P[3];
+        cP[4][q] = 2.0 * w * P[4];
+        cP[5][q] = 2.0 * w * P[5];
+    }
+    __syncthreads();
+    if (need) {
+#pragma unroll
+        for (int k = 0; k < 6; ++k) hb[k] += cP[k][slot];
     }
     if (live) {
 #pragma unroll
