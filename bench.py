@@ -84,6 +84,9 @@ def main():
     ap.add_argument("--only-features", action="store_true",
                     help="just the feature passes, for profiling: the head's 3 scales (quad layout) 4 times, then "
                          "the 512x512x400 volume's single scale in FP32 planar 4 times")
+    ap.add_argument("--only-batch", action="store_true",
+                    help="just the batched leg (64 volumes, autotuned graph launch against per-call launches), for "
+                         "profiling")
     ap.add_argument("--copy-calibration", action="store_true",
                     help="also run a plain 1 GiB device copy (for scaling the HBM counters)")
     args = ap.parse_args()
@@ -102,6 +105,10 @@ def main():
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
     dvr.lib()
+    if args.only_batch:
+        out = leg_batch(dev, torch.cuda.current_stream(), dvr, torch, np, log)
+        print(json.dumps(out), flush=True)
+        return
 
     # ------------------------------------------------------------------ workload (inputs into HBM)
     log("building the head phantom and cameras")
