@@ -17,8 +17,8 @@ import torch
 from . import _abi as abi
 from ._abi import DVRError
 
-__all__ = ["Features", "features", "render", "render_gather", "render_backward", "normalize", "DVRRender", "DVRError",
-           "camera_struct", "lib", "Batch"]
+__all__ = ["Features", "features", "render", "render_gather", "render_backward", "normalize", "DVRRender",
+           "DVRRenderFromVolume", "DVRError", "camera_struct", "lib", "Batch"]
 
 
 def lib():
@@ -357,7 +357,11 @@ def tissue_tf(peaks_buf, colours, taus, tau_hi=0.0, colour_hi=(1.0, 1.0, 1.0)):
 class DVRRender(torch.autograd.Function):
     """rgba = render(vol, TF values) with gradients for the voxel intensities and the TF values
     (knot positions, gradient, k and V are held constant).  The backward is the hand-written adjoint
-    raymarch, which recomputes the samples from the stored per-ray (T_last, k_last)."""
+    raymarch, which recomputes the samples from the stored per-ray (T_last, k_last).
+
+    vol.grad here is the gradient through the TF lookup only: the features are inputs.  For the
+    gradient through the features as well (|grad I| / |grad I|_max, k and V of Eq. 4, computed from
+    vol), use DVRRenderFromVolume."""
 
     @staticmethod
     def forward(ctx, vol, tf_rgba, feats, knots, params, cams):
@@ -373,6 +377,40 @@ class DVRRender(torch.autograd.Function):
                                     k_last, dimg, want_dvol=ctx.needs_input_grad[0])
         return (dvol if ctx.needs_input_grad[0] else None, dtf if ctx.needs_input_grad[1] else None,
                 None, None, None, None)
+
+
+class DVRRenderFromVolume(torch.autograd.Function):
+    """rgba = render(vol, features(vol), TF values): the feature pass runs on vol inside the forward,
+    and the backward chains the render adjoint with feature gradients (dvr_render_backward_features)
+    into the feature-pass adjoint (dvr_features_backward), so vol.grad is the whole dL/dI: through the
+    TF lookup and through the gradient, |grad I|_max, k and the vesselness the raymarch reads.
+
+    apply(vol, tf_rgba, knots, params, cams, spacing, sigmas, alpha, beta, c, layout); c must be > 0
+    (the automatic Frangi c is not differentiated)."""
+
+    @staticmethod
+    def forward(ctx, vol, tf_rgba, knots, params, cams, spacing, sigmas, alpha, beta, c, layout):
+        if not (c > 0):
+            raise ValueError("DVRRenderFromVolume needs an explicit Frangi c > 0")
+        feats = features(vol, spacing, sigmas, alpha=alpha, beta=beta, c=c, layout=layout)
+        rv = vol if layout in (abi.DVR_PLANAR, abi.DVR_SPLIT) else None
+        img, T_last, k_last = render(rv, feats, knots, tf_rgba.contiguous(), params, cams, want_state=True)
+        ctx.save_for_backward(vol, tf_rgba, knots, T_last, k_last)
+        ctx.feats, ctx.params, ctx.cams = feats, params, cams
+        ctx.fp = (spacing, sigmas, alpha, beta, c, layout)
+        return img
+
+    @staticmethod
+    def backward(ctx, dimg):
+        vol, tf_rgba, knots, T_last, k_last = ctx.saved_tensors
+        spacing, sigmas, alpha, beta, c, layout = ctx.fp
+        rv = vol if layout in (abi.DVR_PLANAR, abi.DVR_SPLIT) else None
+        dtf, dvol, fg = render_backward(rv, ctx.feats, knots, tf_rgba.contiguous(), ctx.params, ctx.cams, T_last,
+                                        k_last, dimg, want_dvol=True, want_features=True)
+        if ctx.needs_input_grad[0]:
+            dvol = features_backward(vol, spacing, sigmas, fg, dvol=dvol, alpha=alpha, beta=beta, c=c)
+        return (dvol if ctx.needs_input_grad[0] else None, dtf if ctx.needs_input_grad[1] else None,
+                None, None, None, None, None, None, None, None, None)
 
 
 class Batch:
