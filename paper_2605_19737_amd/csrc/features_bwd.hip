@@ -99,33 +99,66 @@ __device__ __forceinline__ bool maybe_vessel64(const double A[6])
     return !(m00 < -e || d2 < -e2 || d3 < -e3);
 }
 
-// winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0
+// Workgroup list of voxel indices: the lanes with need set append v (one LDS atomic per wave).
+// Every lane of the wave must call it.
+__device__ __forceinline__ void wg_append(bool need, uint32_t v, uint32_t *list, int *count)
+{
+    const uint64_t bal = __ballot(need);
+    if (bal == 0ull) return;
+    const int lead = __ffsll((unsigned long long)bal) - 1;
+    int base = 0;
+    if ((int)(threadIdx.x & 63) == lead) base = atomicAdd(count, __popcll(bal));
+    base = __shfl(base, lead, 64);
+    const int rank = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
+    if (need) list[base + rank] = v;
+}
+
+// Voxels per workgroup of the winning-scale and local-step kernels (kFbSub runs of 256): the few voxels
+// that need the FP64 eigen work are listed over all of them and solved densely, so the lanes of a
+// wave are busy instead of a wave running the solve for its few such lanes.
+constexpr int kFbSub = 4;
+
+// winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0;
+// only the voxels whose V can be non-zero take the eigenvalues (elsewhere V_s = 0, which never beats
+// best >= 0)
 __global__ __launch_bounds__(256) void k_fb_win(const float *__restrict__ H, double *__restrict__ best,
                                                 uint8_t *__restrict__ win, int s, double sigma2, double ia, double ib,
                                                 double ic, uint32_t N)
 {
-    const uint32_t v = blockIdx.x * 256u + threadIdx.x;
-    if (v >= N) return;
-    double A[6];
+    __shared__ uint32_t vl[kFbSub * 256];
+    __shared__ int vcount;
+    if (threadIdx.x == 0) vcount = 0;
+    __syncthreads();
+    for (int j = 0; j < kFbSub; ++j) {
+        const uint32_t v = (blockIdx.x * kFbSub + j) * 256u + threadIdx.x;
+        const bool live = v < N;
+        double A[6];
 #pragma unroll
-    for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
-    double V = 0.0;
-    if (maybe_vessel64(A)) {
+        for (int e = 0; e < 6; ++e) A[e] = live ? sigma2 * (double)H[(size_t)e * N + v] : 0.0;
+        if (live && s == 0) {
+            best[v] = 0.0;
+            win[v] = 255;
+        }
+        wg_append(live && maybe_vessel64(A), v, vl, &vcount);
+    }
+    __syncthreads();
+    const int count = vcount;
+    for (int q = threadIdx.x; q < count; q += 256) {
+        const uint32_t v = vl[q];
+        double A[6];
+#pragma unroll
+        for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
         double lo, mi, hi;
         eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
         double a = lo, b = mi, c = hi, t;
         if (key_less(b, a)) { t = a; a = b; b = t; }
         if (key_less(c, b)) { t = b; b = c; c = t; }
         if (key_less(b, a)) { t = a; a = b; b = t; }
-        V = frangi64(a, b, c, ia, ib, ic);
-    }
-    const double prev = s == 0 ? 0.0 : best[v];
-    if (s == 0) win[v] = 255;
-    if (V > prev) {
-        best[v] = V;
-        win[v] = (uint8_t)s;
-    } else if (s == 0) {
-        best[v] = 0.0;
+        const double V = frangi64(a, b, c, ia, ib, ic);
+        if (V > best[v]) {  // best[v] of this scale's run was written by this workgroup before the barrier
+            best[v] = V;
+            win[v] = (uint8_t)s;
+        }
     }
 }
 
@@ -205,86 +238,78 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
                                                   double ih2)
 {
     const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
-    const uint32_t e = blockIdx.x * 256u + threadIdx.x;
     const int z = (int)blockIdx.y;
-    const bool live = e < plane;
     const size_t N = (size_t)plane * (size_t)nz;
-    const uint32_t v = (uint32_t)z * plane + (live ? e : 0u);
-    double Hd[6];
-#pragma unroll
-    for (int k = 0; k < 6; ++k) Hd[k] = live ? (double)H[(size_t)k * N + v] : 0.0;
-    double hb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+    // the vesselness term (voxels whose winning scale is s and whose dL/dV is not 0, a few per cent)
+    // is listed over the workgroup's kFbSub runs of 256 voxels and solved densely after them
+    __shared__ uint32_t vl[kFbSub * 256];
+    __shared__ int vcount;
+    if (threadIdx.x == 0) vcount = 0;
+    __syncthreads();
     unsigned long long kv = 0ull;
-    if (s == 0 && live) {
-        const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
-        const size_t row = (size_t)z * plane + (size_t)y * nx;
-        const double ixp = ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)), ixm = ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1));
-        const double iyp = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x);
-        const double iym = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x);
-        const double izp = ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x);
-        const double izm = ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x);
-        const double g0 = (ixp - ixm) * ih0, g1 = (iyp - iym) * ih1, g2 = (izp - izm) * ih2;
-        const double gg = g0 * g0 + g1 * g1 + g2 * g2;
-        // the arg-max key takes |g| exactly as the feature pass rounds it: FP32 differences times the
-        // FP32 1/(2h), then grad_norm (the values |g|_max is the maximum of)
-        const float gn32 = grad_norm(((float)ixp - (float)ixm) * (float)ih0, ((float)iyp - (float)iym) * (float)ih1,
-                                     ((float)izp - (float)izm) * (float)ih2);
-        double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
-        const double dk = dfeat[3 * N + v];
-        if (gg > 0.0 && dk != 0.0) {
-            // k = g^T H g / g^T g: dk/dg = 2 (H g - k g) / g^T g, dk/dH_ab = g_a g_b / g^T g (x2 off-diagonal)
-            const double Hg0 = Hd[0] * g0 + Hd[3] * g1 + Hd[4] * g2;
-            const double Hg1 = Hd[3] * g0 + Hd[1] * g1 + Hd[5] * g2;
-            const double Hg2 = Hd[4] * g0 + Hd[5] * g1 + Hd[2] * g2;
-            const double ig = 1.0 / gg;
-            const double k = (g0 * Hg0 + g1 * Hg1 + g2 * Hg2) * ig;
-            const double c2 = 2.0 * dk * ig;
-            d0 += c2 * (Hg0 - k * g0);
-            d1 += c2 * (Hg1 - k * g1);
-            d2 += c2 * (Hg2 - k * g2);
-            const double c1 = dk * ig;
-            hb[0] += c1 * g0 * g0;
-            hb[1] += c1 * g1 * g1;
-            hb[2] += c1 * g2 * g2;
-            hb[3] += 2.0 * c1 * g0 * g1;
-            hb[4] += 2.0 * c1 * g0 * g2;
-            hb[5] += 2.0 * c1 * g1 * g2;
+    for (int j = 0; j < kFbSub; ++j) {
+        const uint32_t e = (blockIdx.x * kFbSub + j) * 256u + threadIdx.x;
+        const bool live = e < plane;
+        const uint32_t v = (uint32_t)z * plane + (live ? e : 0u);
+        double hb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+        if (s == 0 && live) {
+            double Hd[6];
+#pragma unroll
+            for (int k = 0; k < 6; ++k) Hd[k] = (double)H[(size_t)k * N + v];
+            const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
+            const size_t row = (size_t)z * plane + (size_t)y * nx;
+            const double ixp = ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)), ixm = ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1));
+            const double iyp = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x);
+            const double iym = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x);
+            const double izp = ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+            const double izm = ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+            const double g0 = (ixp - ixm) * ih0, g1 = (iyp - iym) * ih1, g2 = (izp - izm) * ih2;
+            const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+            // the arg-max key takes |g| exactly as the feature pass rounds it: FP32 differences times the
+            // FP32 1/(2h), then grad_norm (the values |g|_max is the maximum of)
+            const float gn32 = grad_norm(((float)ixp - (float)ixm) * (float)ih0, ((float)iyp - (float)iym) * (float)ih1,
+                                         ((float)izp - (float)izm) * (float)ih2);
+            double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
+            const double dk = dfeat[3 * N + v];
+            if (gg > 0.0 && dk != 0.0) {
+                // k = g^T H g / g^T g: dk/dg = 2 (H g - k g) / g^T g, dk/dH_ab = g_a g_b / g^T g (x2 off-diagonal)
+                const double Hg0 = Hd[0] * g0 + Hd[3] * g1 + Hd[4] * g2;
+                const double Hg1 = Hd[3] * g0 + Hd[1] * g1 + Hd[5] * g2;
+                const double Hg2 = Hd[4] * g0 + Hd[5] * g1 + Hd[2] * g2;
+                const double ig = 1.0 / gg;
+                const double k = (g0 * Hg0 + g1 * Hg1 + g2 * Hg2) * ig;
+                const double c2 = 2.0 * dk * ig;
+                d0 += c2 * (Hg0 - k * g0);
+                d1 += c2 * (Hg1 - k * g1);
+                d2 += c2 * (Hg2 - k * g2);
+                const double c1 = dk * ig;
+                hb[0] += c1 * g0 * g0;
+                hb[1] += c1 * g1 * g1;
+                hb[2] += c1 * g2 * g2;
+                hb[3] += 2.0 * c1 * g0 * g1;
+                hb[4] += 2.0 * c1 * g0 * g2;
+                hb[5] += 2.0 * c1 * g1 * g2;
+            }
+            dgt[v] = (float)d0;
+            dgt[N + v] = (float)d1;
+            dgt[2 * N + v] = (float)d2;
+            const unsigned long long kk = gkey(gn32, v);
+            kv = kk > kv ? kk : kv;
         }
-        dgt[v] = (float)d0;
-        dgt[N + v] = (float)d1;
-        dgt[2 * N + v] = (float)d2;
-        kv = gkey(gn32, v);
-    }
-    // the vesselness term: voxels whose winning scale is s and whose dL/dV is not 0, compacted over the
-    // workgroup (a few per cent of the voxels; left in place, every wave would run the Jacobi
-    // iteration for its few such lanes) and solved densely, one per lane
-    __shared__ float cH[7][256];      // sigma^2 H (6 entries) and dL/dV of the listed voxels
-    __shared__ double cP[6][256];     // their dL/dH
-    __shared__ int ccount[4];
-    const bool need = live && win[v] == (uint8_t)s && dfeat[4 * N + v] != 0.f;
-    const uint64_t bal = __ballot(need);
-    const int wv = threadIdx.x >> 6;
-    int slot = (int)__builtin_amdgcn_mbcnt_hi((uint32_t)(bal >> 32), __builtin_amdgcn_mbcnt_lo((uint32_t)bal, 0u));
-    if ((threadIdx.x & 63) == 0) ccount[wv] = __popcll(bal);
-    __syncthreads();
-    int count = 0;
+        if (live) {
 #pragma unroll
-    for (int w = 0; w < 4; ++w) {
-        slot += (w < wv) ? ccount[w] : 0;
-        count += ccount[w];
+            for (int k = 0; k < 6; ++k) Hb[(size_t)k * N + v] = (float)hb[k];
+        }
+        wg_append(live && win[v] == (uint8_t)s && dfeat[4 * N + v] != 0.f, v, vl, &vcount);
     }
-    if (need) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) cH[k][slot] = (float)Hd[k];
-        cH[6][slot] = dfeat[4 * N + v];
-    }
-    __syncthreads();
-    if ((int)threadIdx.x < count) {
-        const int q = threadIdx.x;
+    __syncthreads();  // the list, and this workgroup's Hb stores, are complete
+    const int count = vcount;
+    for (int q = threadIdx.x; q < count; q += 256) {
+        const uint32_t v = vl[q];
         double A[6], lam[3], Q[3][3];
 #pragma unroll
-        for (int k = 0; k < 6; ++k) A[k] = sigma2 * (double)cH[k][q];
-        const double dV = cH[6][q];
+        for (int k = 0; k < 6; ++k) A[k] = sigma2 * (double)H[(size_t)k * N + v];
+        const double dV = dfeat[4 * N + v];
         jacobi3v(A, lam, Q);
         int o[3] = {0, 1, 2}, t;
         if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
@@ -293,7 +318,8 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
         const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
         double f[3];
         frangi64_grad(ls, ia, ib, ic, f);
-        // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice)
+        // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice), added to the
+        // k term this workgroup stored for the voxel above
         double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
 #pragma unroll
         for (int i = 0; i < 3; ++i) {
@@ -306,21 +332,11 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
             P[5] += f[i] * x1 * x2;
         }
         const double w = dV * sigma2;
-        cP[0][q] = w * P[0];
-        cP[1][q] = w * P[1];
-        cP[2][q] = w * P[2];
-        cP[3][q] = 2.0 * w * P[3];
-        cP[4][q] = 2.0 * w * P[4];
-        cP[5][q] = 2.0 * w * P[5];
-    }
-    __syncthreads();
-    if (need) {
 #pragma unroll
-        for (int k = 0; k < 6; ++k) hb[k] += cP[k][slot];
-    }
-    if (live) {
-#pragma unroll
-        for (int k = 0; k < 6; ++k) Hb[(size_t)k * N + v] = (float)hb[k];
+        for (int k = 0; k < 6; ++k) {
+            const double add = (k < 3 ? 1.0 : 2.0) * w * P[k];
+            Hb[(size_t)k * N + v] = (float)((double)Hb[(size_t)k * N + v] + add);
+        }
     }
     if (s == 0) {
         for (int o = 32; o > 0; o >>= 1) {
@@ -839,7 +855,8 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     const uint32_t plane = (uint32_t)g.nx * (uint32_t)g.ny;
     const uint32_t N = plane * (uint32_t)g.nz;
     const dim3 pgrid((plane + 255) / 256, g.nz);
-    const dim3 vgrid((N + 255) / 256);
+    const dim3 lgrid((plane + 256 * kFbSub - 1) / (256 * kFbSub), g.nz);  // k_fb_local: kFbSub runs per workgroup
+    const dim3 vgrid((N + 256 * kFbSub - 1) / (256 * kFbSub));             // k_fb_win: likewise
     hipError_t e;
     // band tables of every scale and axis (one launch per scale)
     float *bt[DVR_MAX_SIGMA][3];
@@ -873,11 +890,11 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     for (int s = 0; s < p.nsigma; ++s) {
         float *Hs = w.H + (size_t)6 * N * s;
         if (vol_dt == DVR_F32)
-            hipLaunchKernelGGL(k_fb_local<DVR_F32>, pgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
+            hipLaunchKernelGGL(k_fb_local<DVR_F32>, lgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
                                s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
                                p.inv2h[2]);
         else
-            hipLaunchKernelGGL(k_fb_local<DVR_F16>, pgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
+            hipLaunchKernelGGL(k_fb_local<DVR_F16>, lgrid, dim3(256), 0, st, vol, Hs, dfeat, w.win, w.Hb, w.dgt, w.key,
                                s, p.sigma2[s], p.inv2a2, p.inv2b2, p.inv2c2, g.nx, g.ny, g.nz, p.inv2h[0], p.inv2h[1],
                                p.inv2h[2]);
         float *X = Hs, *Y = w.zws;  // this scale's H is no longer needed
