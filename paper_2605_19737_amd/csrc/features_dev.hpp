@@ -793,6 +793,13 @@ struct XYSlab {
     // issue the loads of slice z
     __device__ __forceinline__ void load(int z)
     {
+        load_rows(z);
+        load_point(z);
+    }
+
+    // the staged rows of slice z (the z pass's three fields over the tile and halo)
+    __device__ __forceinline__ void load_rows(int z)
+    {
         // staged rows: wave wv takes rows wv, wv + NW, ...; a row is W consecutive (clamped) columns,
         // columns lane and 64 + lane, so each row adds only a scalar base to the column offsets
 #pragma unroll
@@ -807,6 +814,12 @@ struct XYSlab {
                 if (two) v1[k] = row[c1];
             }
         }
+    }
+
+    // the intensities of the gradient (first scale) or the V of the earlier scales at this lane's
+    // voxels of slice z
+    __device__ __forceinline__ void load_point(int z)
+    {
         if (a.first) {
             const Buf b = make_buf(a.vol, N * ElemSize<DT>::v);
             const int xp = min(cx + 1, nx - 1), xm = max(cx - 1, 0);
