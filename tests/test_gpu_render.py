@@ -219,7 +219,8 @@ def test_autograd_function():
     torch.testing.assert_close(vol.grad, dvol, rtol=1e-5, atol=1e-7)
 
 
-def test_autograd_through_the_features():
+@pytest.mark.parametrize("layout", [abi.DVR_PLANAR, abi.DVR_QUAD])
+def test_autograd_through_the_features(layout):
     """DVRRenderFromVolume: vol.grad is the render adjoint with feature gradients chained into the
     feature-pass adjoint (the whole dL/dI), the TF gradient that of the render adjoint; against the same
     calls made by hand (the feature gradients are summed with FP32 atomics, so the last bits vary)."""
@@ -229,20 +230,20 @@ def test_autograd_through_the_features():
     c = float(w.c)
     vol = dv.clone().requires_grad_(True)
     tf_p = rg.clone().requires_grad_(True)
-    img = dvr.DVRRenderFromVolume.apply(vol, tf_p, kn, w.params, w.cams, w.spacing, w.sigmas, 0.5, 0.5, c,
-                                        abi.DVR_PLANAR)
+    img = dvr.DVRRenderFromVolume.apply(vol, tf_p, kn, w.params, w.cams, w.spacing, w.sigmas, 0.5, 0.5, c, layout)
     loss = 0.5 * (img ** 2).sum()
     loss.backward()
-    f = dvr.features(dv, w.spacing, w.sigmas, c=c)
-    img2, T, k = dvr.render(dv, f, kn, rg, w.params, w.cams)
+    f = dvr.features(dv, w.spacing, w.sigmas, c=c, layout=layout)
+    rv = dv if layout == abi.DVR_PLANAR else None
+    img2, T, k = dvr.render(rv, f, kn, rg, w.params, w.cams)
     torch.testing.assert_close(img, img2, rtol=0, atol=0)
-    dtf, dvol, fg = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, img2, want_features=True)
+    dtf, dvol, fg = dvr.render_backward(rv, f, kn, rg, w.params, w.cams, T, k, img2, want_features=True)
     dvol = dvr.features_backward(dv, w.spacing, w.sigmas, fg, dvol=dvol, c=c)
     torch.testing.assert_close(tf_p.grad, dtf, rtol=1e-5, atol=1e-6)
     scale = float(dvol.abs().max())
     assert scale > 0 and float((vol.grad - dvol).abs().max()) <= 1e-5 * scale
     # the morphology terms are a real part of it: the TF-lookup part alone differs
-    _, dvol_tf = dvr.render_backward(dv, f, kn, rg, w.params, w.cams, T, k, img2)
+    _, dvol_tf = dvr.render_backward(rv, f, kn, rg, w.params, w.cams, T, k, img2)
     assert float((vol.grad - dvol_tf).abs().max()) > 1e-3 * scale
 
 
