@@ -12,8 +12,8 @@
 // scale:
 //   1. k_fb_local (FP64, one lane per voxel) forms dL/dH: the curvature term g g^T / g^T g at the
 //      first scale, and at the voxel's winning scale dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T from
-//      a Jacobi eigen-decomposition; at the first scale it also writes dL/dg + dL/dk dk/dg and
-//      the arg-max key of |g|;
+//      a Jacobi eigen-decomposition (those voxels listed over the workgroup's 1024 and solved one per
+//      lane); at the first scale it also writes dL/dg + dL/dk dk/dg and the arg-max key of |g|;
 //   2. the x, y and z transposes apply the transposed operators (the forward's z-then-y-then-x order
 //      reversed: six fields after x, three after y, one accumulated into dL/dI after z): for radii
 //      2..10 k_tx_lds_r, k_ty_run_r, k_tz_run_r, else k_tx_lds (k_tx), k_ty_run, k_tz_run.
@@ -113,52 +113,40 @@ __device__ __forceinline__ void wg_append(bool need, uint32_t v, uint32_t *list,
     if (need) list[base + rank] = v;
 }
 
-// Voxels per workgroup of the winning-scale and local-step kernels (kFbSub runs of 256): the few voxels
-// that need the FP64 eigen work are listed over all of them and solved densely, so the lanes of a
-// wave are busy instead of a wave running the solve for its few such lanes.
+// Voxels per workgroup of the local-step kernel (kFbSub runs of 256): the few voxels that need the
+// FP64 eigen work are listed over all of them and solved densely, so the lanes of a wave are busy
+// instead of a wave running the solve for its few such lanes.
 constexpr int kFbSub = 4;
 
-// winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0;
-// only the voxels whose V can be non-zero take the eigenvalues (elsewhere V_s = 0, which never beats
-// best >= 0)
+// winning scale: V_s in FP64 (closed-form eigenvalues), the first scale above every earlier one and 0,
+// one lane per voxel (its time is bound by reading the Hessians: listing the few voxels that take the
+// eigenvalues, as the local step does, made it slower)
 __global__ __launch_bounds__(256) void k_fb_win(const float *__restrict__ H, double *__restrict__ best,
                                                 uint8_t *__restrict__ win, int s, double sigma2, double ia, double ib,
                                                 double ic, uint32_t N)
 {
-    __shared__ uint32_t vl[kFbSub * 256];
-    __shared__ int vcount;
-    if (threadIdx.x == 0) vcount = 0;
-    __syncthreads();
-    for (int j = 0; j < kFbSub; ++j) {
-        const uint32_t v = (blockIdx.x * kFbSub + j) * 256u + threadIdx.x;
-        const bool live = v < N;
-        double A[6];
+    const uint32_t v = blockIdx.x * 256u + threadIdx.x;
+    if (v >= N) return;
+    double A[6];
 #pragma unroll
-        for (int e = 0; e < 6; ++e) A[e] = live ? sigma2 * (double)H[(size_t)e * N + v] : 0.0;
-        if (live && s == 0) {
-            best[v] = 0.0;
-            win[v] = 255;
-        }
-        wg_append(live && maybe_vessel64(A), v, vl, &vcount);
-    }
-    __syncthreads();
-    const int count = vcount;
-    for (int q = threadIdx.x; q < count; q += 256) {
-        const uint32_t v = vl[q];
-        double A[6];
-#pragma unroll
-        for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
+    for (int e = 0; e < 6; ++e) A[e] = sigma2 * (double)H[(size_t)e * N + v];
+    double V = 0.0;
+    if (maybe_vessel64(A)) {
         double lo, mi, hi;
         eig_trig<double>(A[0], A[1], A[2], A[3], A[4], A[5], lo, mi, hi);
         double a = lo, b = mi, c = hi, t;
         if (key_less(b, a)) { t = a; a = b; b = t; }
         if (key_less(c, b)) { t = b; b = c; c = t; }
         if (key_less(b, a)) { t = a; a = b; b = t; }
-        const double V = frangi64(a, b, c, ia, ib, ic);
-        if (V > best[v]) {  // best[v] of this scale's run was written by this workgroup before the barrier
-            best[v] = V;
-            win[v] = (uint8_t)s;
-        }
+        V = frangi64(a, b, c, ia, ib, ic);
+    }
+    const double prev = s == 0 ? 0.0 : best[v];
+    if (s == 0) win[v] = 255;
+    if (V > prev) {
+        best[v] = V;
+        win[v] = (uint8_t)s;
+    } else if (s == 0) {
+        best[v] = 0.0;
     }
 }
 
@@ -856,7 +844,7 @@ hipError_t launch_features_backward(const void *vol, int vol_dt, const dvr_grid 
     const uint32_t N = plane * (uint32_t)g.nz;
     const dim3 pgrid((plane + 255) / 256, g.nz);
     const dim3 lgrid((plane + 256 * kFbSub - 1) / (256 * kFbSub), g.nz);  // k_fb_local: kFbSub runs per workgroup
-    const dim3 vgrid((N + 256 * kFbSub - 1) / (256 * kFbSub));             // k_fb_win: likewise
+    const dim3 vgrid((N + 255) / 256);
     hipError_t e;
     // band tables of every scale and axis (one launch per scale)
     float *bt[DVR_MAX_SIGMA][3];
