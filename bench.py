@@ -196,6 +196,14 @@ def main():
     # the counters' same-address atomics would otherwise add ~0.15 ms per view to the timed raymarch)
     dvr.render(vol, feats, knots, tf, w.params, cams, out=img, counters=counters)
     evaluated, shaded = (int(x) for x in counters.cpu().tolist())
+    # nominal samples (every segment midpoint of every ray, no early termination): the same walk with a
+    # TF of zero extinction everywhere, whose rays all run to the end of their chord, untimed
+    tf_clear = tf.clone()
+    tf_clear[:, 3] = 0.0
+    p_clear = dict(w.params)
+    p_clear["et_alpha"] = 0.0
+    dvr.render(vol, feats, knots, tf_clear, p_clear, cams, out=img, counters=counters)
+    nominal = int(counters[0].item())
     log(f"step {1e3 * t_step / args.steps:.2f} ms (features {1e3 * t_feat / args.steps:.3f} ms, render "
         f"{1e3 * t_rend / args.steps:.2f} ms); samples/step evaluated {evaluated:.4g} shaded {shaded:.4g}; wall {wall:.2f}s")
 
@@ -254,7 +262,8 @@ def main():
              "features_valu_frac": FEAT_FLOP_3SCALE * vox_per_s / (PEAK_FP32_TFLOPS * 1e12),
              "render_samples_per_s": render_sps, "render_ms_per_view": 1e3 * t_rend / (K * V),
              "samples_evaluated_per_step": evaluated, "samples_shaded_per_step": shaded,
-             "rays_per_step": V * 1024 * 1024}
+             "rays_per_step": V * 1024 * 1024, "samples_nominal_per_step": nominal,
+             "nominal_samples_per_s": nominal * K / t_step}
 
     # ------------------------------------------------------------------ fwd+bwd ms/view leg
     if args.only_main:
