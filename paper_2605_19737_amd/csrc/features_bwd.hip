@@ -217,6 +217,115 @@ __device__ __forceinline__ unsigned long long gkey(float gn, uint32_t v)
     return ((unsigned long long)__float_as_uint(gn) << 32) | (unsigned long long)(0xffffffffu - v);
 }
 
+// The curvature part of the local step at one voxel of the first scale (x, y, z; v its index): adds
+// dL/dk dk/dH to hb, writes dL/dg + dL/dk dk/dg of the voxel to dgt when wr is set, and returns the
+// arg-max key of |g|
+template <int DT>
+__device__ __forceinline__ unsigned long long local_k(const void *__restrict__ vol, const float *__restrict__ H,
+                                                      const float *__restrict__ dfeat, float *__restrict__ dgt,
+                                                      uint32_t v, int x, int y, int z, int nx, int ny, int nz,
+                                                      size_t N, double ih0, double ih1, double ih2, bool wr,
+                                                      double hb[6])
+{
+    const uint32_t plane = (uint32_t)nx * (uint32_t)ny;
+    double Hd[6];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) Hd[k] = (double)H[(size_t)k * N + v];
+    const size_t row = (size_t)z * plane + (size_t)y * nx;
+    const double ixp = ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)), ixm = ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1));
+    const double iyp = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x);
+    const double iym = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x);
+    const double izp = ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+    const double izm = ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x);
+    const double g0 = (ixp - ixm) * ih0, g1 = (iyp - iym) * ih1, g2 = (izp - izm) * ih2;
+    const double gg = g0 * g0 + g1 * g1 + g2 * g2;
+    // the arg-max key takes |g| exactly as the feature pass rounds it: FP32 differences times the
+    // FP32 1/(2h), then grad_norm (the values |g|_max is the maximum of)
+    const float gn32 = grad_norm(((float)ixp - (float)ixm) * (float)ih0, ((float)iyp - (float)iym) * (float)ih1,
+                                 ((float)izp - (float)izm) * (float)ih2);
+    double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
+    const double dk = dfeat[3 * N + v];
+    if (gg > 0.0 && dk != 0.0) {
+        // k = g^T H g / g^T g: dk/dg = 2 (H g - k g) / g^T g, dk/dH_ab = g_a g_b / g^T g (x2 off-diagonal)
+        const double Hg0 = Hd[0] * g0 + Hd[3] * g1 + Hd[4] * g2;
+        const double Hg1 = Hd[3] * g0 + Hd[1] * g1 + Hd[5] * g2;
+        const double Hg2 = Hd[4] * g0 + Hd[5] * g1 + Hd[2] * g2;
+        const double ig = 1.0 / gg;
+        const double k = (g0 * Hg0 + g1 * Hg1 + g2 * Hg2) * ig;
+        const double c2 = 2.0 * dk * ig;
+        d0 += c2 * (Hg0 - k * g0);
+        d1 += c2 * (Hg1 - k * g1);
+        d2 += c2 * (Hg2 - k * g2);
+        const double c1 = dk * ig;
+        hb[0] += c1 * g0 * g0;
+        hb[1] += c1 * g1 * g1;
+        hb[2] += c1 * g2 * g2;
+        hb[3] += 2.0 * c1 * g0 * g1;
+        hb[4] += 2.0 * c1 * g0 * g2;
+        hb[5] += 2.0 * c1 * g1 * g2;
+    }
+    if (wr) {
+        dgt[v] = (float)d0;
+        dgt[N + v] = (float)d1;
+        dgt[2 * N + v] = (float)d2;
+    }
+    return gkey(gn32, v);
+}
+
+// The vesselness part of the local step at a voxel whose winning scale is this one: dL/dH =
+// dL/dV sigma^2 sum_i dV/dlambda_i e_i e_i^T (off-diagonal entries counted twice), from a Jacobi
+// eigen-decomposition of sigma^2 H
+__device__ __forceinline__ void local_v(const float *__restrict__ H, const float *__restrict__ dfeat, uint32_t v,
+                                        size_t N, double sigma2, double ia, double ib, double ic, double add[6])
+{
+    double A[6], lam[3], Q[3][3];
+#pragma unroll
+    for (int k = 0; k < 6; ++k) A[k] = sigma2 * (double)H[(size_t)k * N + v];
+    const double dV = dfeat[4 * N + v];
+    jacobi3v(A, lam, Q);
+    int o[3] = {0, 1, 2}, t;
+    if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+    if (key_less(lam[o[2]], lam[o[1]])) { t = o[1]; o[1] = o[2]; o[2] = t; }
+    if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
+    const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
+    double f[3];
+    frangi64_grad(ls, ia, ib, ic, f);
+    double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+#pragma unroll
+    for (int i = 0; i < 3; ++i) {
+        const double x0 = Q[0][o[i]], x1 = Q[1][o[i]], x2 = Q[2][o[i]];
+        P[0] += f[i] * x0 * x0;
+        P[1] += f[i] * x1 * x1;
+        P[2] += f[i] * x2 * x2;
+        P[3] += f[i] * x0 * x1;
+        P[4] += f[i] * x0 * x2;
+        P[5] += f[i] * x1 * x2;
+    }
+    const double w = dV * sigma2;
+#pragma unroll
+    for (int k = 0; k < 6; ++k) add[k] = (k < 3 ? 1.0 : 2.0) * w * P[k];
+}
+
+// workgroup maximum of the arg-max keys, then one atomic when it beats the current maximum: atomics on
+// one address serialize in the L2, and one per wave cost about a millisecond on the head (a stale
+// read of the key is never above the true maximum, so skipping stays exact).  Every thread of the
+// 256-lane workgroup must be here.
+__device__ __forceinline__ void key_max(unsigned long long kv, unsigned long long *__restrict__ key)
+{
+    for (int o = 32; o > 0; o >>= 1) {
+        const unsigned long long w = __shfl_xor(kv, o, 64);
+        kv = w > kv ? w : kv;
+    }
+    __shared__ unsigned long long wkey[4];
+    if ((threadIdx.x & 63) == 0) wkey[threadIdx.x >> 6] = kv;
+    __syncthreads();
+    if (threadIdx.x == 0) {
+#pragma unroll
+        for (int k = 1; k < 4; ++k) kv = wkey[k] > kv ? wkey[k] : kv;
+        if (kv != 0ull && kv > __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(key, kv);
+    }
+}
+
 template <int DT>
 __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, const float *__restrict__ H,
                                                   const float *__restrict__ dfeat, const uint8_t *__restrict__ win,
@@ -241,47 +350,8 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
         const uint32_t v = (uint32_t)z * plane + (live ? e : 0u);
         double hb[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
         if (s == 0 && live) {
-            double Hd[6];
-#pragma unroll
-            for (int k = 0; k < 6; ++k) Hd[k] = (double)H[(size_t)k * N + v];
             const int y = (int)(e / (uint32_t)nx), x = (int)(e - (uint32_t)y * nx);
-            const size_t row = (size_t)z * plane + (size_t)y * nx;
-            const double ixp = ldd<DT>(vol, row + clampi(x + 1, 0, nx - 1)), ixm = ldd<DT>(vol, row + clampi(x - 1, 0, nx - 1));
-            const double iyp = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y + 1, 0, ny - 1) * nx + x);
-            const double iym = ldd<DT>(vol, (size_t)z * plane + (size_t)clampi(y - 1, 0, ny - 1) * nx + x);
-            const double izp = ldd<DT>(vol, (size_t)clampi(z + 1, 0, nz - 1) * plane + (size_t)y * nx + x);
-            const double izm = ldd<DT>(vol, (size_t)clampi(z - 1, 0, nz - 1) * plane + (size_t)y * nx + x);
-            const double g0 = (ixp - ixm) * ih0, g1 = (iyp - iym) * ih1, g2 = (izp - izm) * ih2;
-            const double gg = g0 * g0 + g1 * g1 + g2 * g2;
-            // the arg-max key takes |g| exactly as the feature pass rounds it: FP32 differences times the
-            // FP32 1/(2h), then grad_norm (the values |g|_max is the maximum of)
-            const float gn32 = grad_norm(((float)ixp - (float)ixm) * (float)ih0, ((float)iyp - (float)iym) * (float)ih1,
-                                         ((float)izp - (float)izm) * (float)ih2);
-            double d0 = dfeat[v], d1 = dfeat[N + v], d2 = dfeat[2 * N + v];
-            const double dk = dfeat[3 * N + v];
-            if (gg > 0.0 && dk != 0.0) {
-                // k = g^T H g / g^T g: dk/dg = 2 (H g - k g) / g^T g, dk/dH_ab = g_a g_b / g^T g (x2 off-diagonal)
-                const double Hg0 = Hd[0] * g0 + Hd[3] * g1 + Hd[4] * g2;
-                const double Hg1 = Hd[3] * g0 + Hd[1] * g1 + Hd[5] * g2;
-                const double Hg2 = Hd[4] * g0 + Hd[5] * g1 + Hd[2] * g2;
-                const double ig = 1.0 / gg;
-                const double k = (g0 * Hg0 + g1 * Hg1 + g2 * Hg2) * ig;
-                const double c2 = 2.0 * dk * ig;
-                d0 += c2 * (Hg0 - k * g0);
-                d1 += c2 * (Hg1 - k * g1);
-                d2 += c2 * (Hg2 - k * g2);
-                const double c1 = dk * ig;
-                hb[0] += c1 * g0 * g0;
-                hb[1] += c1 * g1 * g1;
-                hb[2] += c1 * g2 * g2;
-                hb[3] += 2.0 * c1 * g0 * g1;
-                hb[4] += 2.0 * c1 * g0 * g2;
-                hb[5] += 2.0 * c1 * g1 * g2;
-            }
-            dgt[v] = (float)d0;
-            dgt[N + v] = (float)d1;
-            dgt[2 * N + v] = (float)d2;
-            const unsigned long long kk = gkey(gn32, v);
+            const unsigned long long kk = local_k<DT>(vol, H, dfeat, dgt, v, x, y, z, nx, ny, nz, N, ih0, ih1, ih2, true, hb);
             kv = kk > kv ? kk : kv;
         }
         if (live) {
@@ -294,55 +364,13 @@ __global__ __launch_bounds__(256) void k_fb_local(const void *__restrict__ vol, 
     const int count = vcount;
     for (int q = threadIdx.x; q < count; q += 256) {
         const uint32_t v = vl[q];
-        double A[6], lam[3], Q[3][3];
+        double add[6];
+        local_v(H, dfeat, v, N, sigma2, ia, ib, ic, add);
+        // added to the k term this workgroup stored for the voxel above
 #pragma unroll
-        for (int k = 0; k < 6; ++k) A[k] = sigma2 * (double)H[(size_t)k * N + v];
-        const double dV = dfeat[4 * N + v];
-        jacobi3v(A, lam, Q);
-        int o[3] = {0, 1, 2}, t;
-        if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
-        if (key_less(lam[o[2]], lam[o[1]])) { t = o[1]; o[1] = o[2]; o[2] = t; }
-        if (key_less(lam[o[1]], lam[o[0]])) { t = o[0]; o[0] = o[1]; o[1] = t; }
-        const double ls[3] = {lam[o[0]], lam[o[1]], lam[o[2]]};
-        double f[3];
-        frangi64_grad(ls, ia, ib, ic, f);
-        // dL/dH = dV sigma^2 sum_i f_i e_i e_i^T (off-diagonal entries counted twice), added to the
-        // k term this workgroup stored for the voxel above
-        double P[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
-#pragma unroll
-        for (int i = 0; i < 3; ++i) {
-            const double x0 = Q[0][o[i]], x1 = Q[1][o[i]], x2 = Q[2][o[i]];
-            P[0] += f[i] * x0 * x0;
-            P[1] += f[i] * x1 * x1;
-            P[2] += f[i] * x2 * x2;
-            P[3] += f[i] * x0 * x1;
-            P[4] += f[i] * x0 * x2;
-            P[5] += f[i] * x1 * x2;
-        }
-        const double w = dV * sigma2;
-#pragma unroll
-        for (int k = 0; k < 6; ++k) {
-            const double add = (k < 3 ? 1.0 : 2.0) * w * P[k];
-            Hb[(size_t)k * N + v] = (float)((double)Hb[(size_t)k * N + v] + add);
-        }
+        for (int k = 0; k < 6; ++k) Hb[(size_t)k * N + v] = (float)((double)Hb[(size_t)k * N + v] + add[k]);
     }
-    if (s == 0) {
-        for (int o = 32; o > 0; o >>= 1) {
-            const unsigned long long w = __shfl_xor(kv, o, 64);
-            kv = w > kv ? w : kv;
-        }
-        // one key per workgroup, and an atomic only when it beats the current maximum: atomics on
-        // one address serialize in the L2, and one per wave cost about a millisecond on the head
-        // (a stale read of the key is never above the true maximum, so skipping stays exact)
-        __shared__ unsigned long long wkey[4];
-        if ((threadIdx.x & 63) == 0) wkey[threadIdx.x >> 6] = kv;
-        __syncthreads();
-        if (threadIdx.x == 0) {
-#pragma unroll
-            for (int k = 1; k < 4; ++k) kv = wkey[k] > kv ? wkey[k] : kv;
-            if (kv != 0ull && kv > __hip_atomic_load(key, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) atomicMax(key, kv);
-        }
-    }
+    if (s == 0) key_max(kv, key);
 }
 
 // x: six fields X_e = (operator of entry e along x)^T Hb_e; xx uses D2 G, xy and xz D1 G, the rest G

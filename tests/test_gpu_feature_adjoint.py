@@ -126,7 +126,9 @@ def _vessel_crop(shape, seed):
     that makes the |g| maximum unique."""
     w = phantoms.c3(32, 32, views=[0])
     nz, ny, nx = shape
-    v = w.vol[30:30 + nz, 35:35 + ny, 28:28 + nx].astype(np.float64).copy()
+    v = w.vol[30:30 + nz, 35:35 + ny, 28:28 + min(nx, 90)].astype(np.float64)
+    # longer rows repeat the crop mirrored, so that rows span several x chunks of the adjoint kernels
+    v = np.concatenate([v, v[:, :, ::-1]] * (1 + nx // 180), axis=2)[:, :, :nx].copy()
     v[nz // 2, ny // 3, nx // 4] += 0.6
     return v
 
@@ -135,6 +137,9 @@ def _vessel_crop(shape, seed):
     ((23, 29, 37), (1.0, 0.8, 1.3), [1.0, 1.6], torch.float32),
     ((40, 70, 90), (0.9, 0.9, 1.2), [1.0, 2.0, 3.0], torch.float32),
     ((17, 19, 66), (0.7, 1.1, 2.5), [0.8], torch.float16),
+    # rows of 530 voxels: several x chunks per row (236..252 outputs each at the radii 2..10)
+    ((6, 9, 530), (1.0, 1.0, 1.0), [0.7, 1.5, 3.0], torch.float32),
+    ((5, 6, 300), (1.0, 1.0, 1.0), [1.2], torch.float16),
     ((2, 3, 5), (1.0, 1.0, 1.0), [1.0, 1.5], torch.float32),
     ((2, 2, 2), (1.0, 1.0, 1.0), [1.0, 1.5], torch.float32),
     # eight scales (the most the ABI takes); radii up to 12 take the generic Hessian kernels
