@@ -134,7 +134,8 @@ typedef struct dvr_render_params {
 
 /* Camera, pixel (i, j) with row j = 0 at the top:
  *   orthographic (persp = 0): origin o + (i+1/2) du + (j+1/2) dv, direction d0 (unit length);
- *   perspective  (persp = 1): origin o, direction normalize(d0 + (i+1/2) du + (j+1/2) dv). */
+ *   perspective  (persp = 1): origin o, direction normalize(d0 + (i+1/2) du + (j+1/2) dv).
+ * 1 <= width, height <= 2^23 (DVR_E_INVALID_ARG otherwise). */
 typedef struct dvr_camera {
     int32_t persp, width, height;
     float o[3], d0[3], du[3], dv[3];

@@ -451,6 +451,8 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
     if (!cams || ncam < 1) return fail(DVR_E_INVALID_ARG, "need at least one camera");
     const int W = cams[0].width, H = cams[0].height;
     if (W < 1 || H < 1) return fail(DVR_E_INVALID_ARG, "image size must be >= 1");
+    // pixel centres i + 1/2 are exact FP32 numbers below 2^23 (the ray setup's double-float FP32)
+    if (W > (1 << 23) || H > (1 << 23)) return fail(DVR_E_INVALID_ARG, "image width and height must not exceed 2^23");
     if ((double)W * H * ncam > 2147483647.0) return fail(DVR_E_INVALID_ARG, "too many pixels");
     for (int i = 0; i < ncam; ++i) {
         const dvr_camera &c = cams[i];
@@ -482,13 +484,8 @@ dvr_status dvr::host::build_render_args(const void *vol, int32_t vol_dtype, cons
     a.grid.n[0] = grid->nx;
     a.grid.n[1] = grid->ny;
     a.grid.n[2] = grid->nz;
-    a.grid.h[0] = grid->hx;
-    a.grid.h[1] = grid->hy;
-    a.grid.h[2] = grid->hz;
-    double hmin = grid->hx;
-    if (grid->hy < hmin) hmin = grid->hy;
-    if (grid->hz < hmin) hmin = grid->hz;
-    a.grid.delta = (double)rp->step_vox * hmin;
+    const float hg[3] = {grid->hx, grid->hy, grid->hz};
+    dvr::set_grid_steps(a.grid, hg, rp->step_vox);
     a.tf.K = tf->K;
     a.tf.knots = tf->knots;
     a.tf.rgba = tf->rgba;

@@ -56,8 +56,7 @@ struct BVol {
     void *vtmp;   // quad layout: V as a plain field (features dtype) until the Q items build its quads
     int32_t n[3];
     int32_t tiles_x;
-    double h[3];
-    double delta;
+    KGrid grid;  // extents, spacings and segment length for the ray setup
     float inv2h[3];
 };
 
@@ -307,12 +306,17 @@ __global__ __launch_bounds__(256, 3) void k_batch(BatchArgs A)
             f.layout = LAYOUT;
             f.bricks = nullptr;  // the batched launch builds no brick tables
             f.nb[0] = f.nb[1] = f.nb[2] = 0;
-            KGrid g;
+            KGrid g;  // field by field: V lives in the constant address space
             for (int k = 0; k < 3; ++k) {
-                g.n[k] = V.n[k];
-                g.h[k] = V.h[k];
+                g.n[k] = V.grid.n[k];
+                g.h[k] = V.grid.h[k];
+                g.ih_hi[k] = V.grid.ih_hi[k];
+                g.ih_lo[k] = V.grid.ih_lo[k];
             }
-            g.delta = V.delta;
+            g.delta_hi = V.grid.delta_hi;
+            g.delta_lo = V.grid.delta_lo;
+            g.idelta_hi = V.grid.idelta_hi;
+            g.idelta_lo = V.grid.idelta_lo;
             const float gm = __hip_atomic_load(V.gmax, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
             const float invg = gm > 0.f ? 1.f / gm : 0.f;
             int pi, pj;
@@ -479,11 +483,12 @@ extern "C" dvr_status dvr_batch_create(const dvr_batch_desc *d, dvr_batch **plan
         B.n[1] = bv.grid.ny;
         B.n[2] = bv.grid.nz;
         B.tiles_x = (bv.grid.nx + TX - 1) / TX;
-        for (int a = 0; a < 3; ++a) {
-            B.h[a] = h[a];
-            B.inv2h[a] = (float)(1.0 / (2.0 * h[a]));
-        }
-        B.delta = (double)d->rp.step_vox * std::min(h[0], std::min(h[1], h[2]));
+        for (int a = 0; a < 3; ++a) B.inv2h[a] = (float)(1.0 / (2.0 * h[a]));
+        const float hf[3] = {bv.grid.hx, bv.grid.hy, bv.grid.hz};
+        B.grid.n[0] = bv.grid.nx;
+        B.grid.n[1] = bv.grid.ny;
+        B.grid.n[2] = bv.grid.nz;
+        set_grid_steps(B.grid, hf, d->rp.step_vox);
         for (int sc = 0; sc < ns; ++sc) {
             ScaleTaps &t = taps[(size_t)v * ns + sc];
             for (int a = 0; a < 3; ++a) axis_taps((double)fp.sigma_mm[sc] / h[a], h[a], t.ax[a]);

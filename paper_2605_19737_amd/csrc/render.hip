@@ -6,8 +6,9 @@
 // loop empties), which is the wave-ballot early termination.
 //
 // Ray geometry.  The camera ray, the slab clip against [0,(n-1)h] and the segment count are
-// computed once per ray in IEEE double with the same operation order as the FP64 definition (no
-// FMA contraction), so N and the segment lengths agree with it.  Sample positions in voxel units
+// computed once per ray in double-float FP32 (pairs of FP32 numbers, ~48 bits, from error-free
+// transforms), following the FP64 definition's steps, so N and the segment lengths agree with it
+// (plain FP32 here moves the head's perspective images by ~6e-4).  Sample positions in voxel units
 // are then carried in 32.32 fixed point: q_k = q_0 + k dq for the full segments and the midpoint
 // of the shorter last segment separately.  Integer steps are exact and reversible, so the adjoint
 // walks the same positions back to front, and the clamp of the first and last positions (plus a

@@ -26,8 +26,11 @@ struct KFeat {
 
 struct KGrid {
     int32_t n[3];
-    double h[3];
-    double delta;  // step_vox * min(h), mm
+    float h[3];
+    float delta_hi, delta_lo;    // step_vox * min(h) in mm, exactly: the sum of the two (the product of
+                                 // two FP32 numbers has at most 48 significant bits)
+    float ih_hi[3], ih_lo[3];    // 1 / h as a double-float pair (~48 bits)
+    float idelta_hi, idelta_lo;  // 1 / (step_vox * min(h)) likewise
 };
 
 struct KTF {
@@ -63,5 +66,27 @@ struct RenderArgs {
     const KCam *cams;
     int32_t ncam;
 };
+
+// Host: a double as the pair hi + lo of FP32 numbers (exact for the 48-bit product step_vox * hmin).
+inline void split2(double v, float &hi, float &lo)
+{
+    hi = (float)v;
+    lo = (float)(v - (double)hi);
+}
+
+// the grid's spacing and segment-length fields of KGrid, from the FP32 spacings and step
+inline void set_grid_steps(KGrid &g, const float h[3], float step_vox)
+{
+    float hmin = h[0];
+    if (h[1] < hmin) hmin = h[1];
+    if (h[2] < hmin) hmin = h[2];
+    const double d = (double)step_vox * (double)hmin;
+    split2(d, g.delta_hi, g.delta_lo);
+    split2(1.0 / d, g.idelta_hi, g.idelta_lo);
+    for (int a = 0; a < 3; ++a) {
+        g.h[a] = h[a];
+        split2(1.0 / (double)h[a], g.ih_hi[a], g.ih_lo[a]);
+    }
+}
 
 }  // namespace dvr

@@ -11,8 +11,6 @@
 
 namespace dvr {
 
-constexpr double kS32 = 4294967296.0;
-
 struct RayGeo {
     int N;               // number of segments (0 = miss)
     int64_t q0[3];       // fixed-point position of sample 0
@@ -22,63 +20,192 @@ struct RayGeo {
     float delta, dlast;  // segment lengths (mm)
 };
 
-__device__ __forceinline__ int64_t to_fix(double q, int n)
+// ------------------------------------------------------------------------------------------------
+// Double-float arithmetic for the per-ray geometry: a value is the unevaluated sum hi + lo of two
+// FP32 numbers with |lo| <= ulp(hi) / 2 (about 48 significant bits), built on the error-free
+// transforms TwoSum (Knuth) and TwoProd (one fused multiply-add), as in Dekker's 1971 double-length
+// arithmetic.  A quotient takes three terms from the hardware reciprocal (about 1 ulp), each
+// correcting the exact residual of the previous ones, and a square root one Newton step; neither
+// needs a correctly rounded FP32 division.  Operation order matters: no contraction is applied to
+// these (every fused multiply-add is explicit).
+struct F2 {
+    float hi, lo;
+};
+
+__device__ __forceinline__ F2 f2(float a) { return {a, 0.f}; }
+
+__device__ __forceinline__ F2 two_sum(float a, float b)
 {
-    double v = q * kS32;
-    const double hi = (double)(n - 1) * kS32 - 1.0;
-    v = v < 0.0 ? 0.0 : (v > hi ? hi : v);
-    return (int64_t)__double2ll_rn(v);
+    const float s = a + b, bb = s - a;
+    return {s, (a - (s - bb)) + (b - bb)};
 }
 
+// exact when |a| >= |b| (or a = 0)
+__device__ __forceinline__ F2 fast_two_sum(float a, float b)
+{
+    const float s = a + b;
+    return {s, b - (s - a)};
+}
+
+__device__ __forceinline__ F2 two_prod(float a, float b)
+{
+    const float p = a * b;
+    return {p, fmaf(a, b, -p)};
+}
+
+// Dekker's addition: the error is below ~2^-47 of max(|a|, |b|) (not relative to a cancelled sum,
+// which is all the geometry needs: its inputs carry that absolute precision already)
+__device__ __forceinline__ F2 f2_add(F2 a, F2 b)
+{
+    const F2 s = two_sum(a.hi, b.hi);
+    return fast_two_sum(s.hi, s.lo + (a.lo + b.lo));
+}
+
+__device__ __forceinline__ F2 f2_neg(F2 a) { return {-a.hi, -a.lo}; }
+
+__device__ __forceinline__ F2 f2_sub(F2 a, F2 b) { return f2_add(a, f2_neg(b)); }
+
+__device__ __forceinline__ F2 f2_mul(F2 a, F2 b)
+{
+    const F2 p = two_prod(a.hi, b.hi);
+    return fast_two_sum(p.hi, fmaf(a.hi, b.lo, fmaf(a.lo, b.hi, p.lo)));
+}
+
+__device__ __forceinline__ F2 f2_mulf(F2 a, float b)
+{
+    const F2 p = two_prod(a.hi, b);
+    return fast_two_sum(p.hi, fmaf(a.lo, b, p.lo));
+}
+
+__device__ __forceinline__ F2 f2_half(F2 a) { return {0.5f * a.hi, 0.5f * a.lo}; }
+
+// 1 / b (b finite and non-zero)
+__device__ __forceinline__ F2 f2_recip(F2 b)
+{
+    const float rb = __builtin_amdgcn_rcpf(b.hi);
+    const float q1 = rb;
+    const F2 r1 = f2_sub(f2(1.f), f2_mulf(b, q1));
+    const float q2 = r1.hi * rb;
+    const F2 r2 = f2_sub(r1, f2_mulf(b, q2));
+    return fast_two_sum(q1, q2 + r2.hi * rb);
+}
+
+// a > 0
+__device__ __forceinline__ F2 f2_sqrt(F2 a)
+{
+    const float s = __builtin_amdgcn_sqrtf(a.hi);
+    const F2 e = f2_sub(a, two_prod(s, s));
+    return fast_two_sum(s, e.hi * (0.5f * __builtin_amdgcn_rcpf(s)));
+}
+
+__device__ __forceinline__ bool f2_lt(F2 a, F2 b) { return a.hi < b.hi || (a.hi == b.hi && a.lo < b.lo); }
+
+// nearest integer of a finite value of magnitude below 2^62: the integer-valued high part is split
+// toward zero into a multiple of 2^32 and a remainder of the same sign below 2^32 in magnitude (both
+// exact FP32 integers), each converted with a 32-bit conversion
+__device__ __forceinline__ int64_t f2_rint(F2 a)
+{
+    const float h = rintf(a.hi);
+    const float r = rintf((a.hi - h) + a.lo);
+    const float hh = truncf(h * 0x1p-32f);
+    const float hl = h - hh * 0x1p32f;
+    const int64_t lo = hl >= 0.f ? (int64_t)(uint32_t)hl : -(int64_t)(uint32_t)(-hl);
+    return (int64_t)((uint64_t)(int64_t)(int32_t)hh << 32) + lo + (int64_t)(int32_t)r;
+}
+
+// a * 2^32 to the nearest fixed-point position, clamped to [0, (n - 1) 2^32 - 1]
+__device__ __forceinline__ int64_t to_fix(F2 q, int n)
+{
+    const int64_t hi = (int64_t)(n - 1) * 4294967296LL - 1;
+    const F2 v = {q.hi * 4294967296.f, q.lo * 4294967296.f};
+    if (!(v.hi > -1.f)) return 0;  // also NaN
+    if (!(v.hi < 4.0e18f)) return hi;
+    const int64_t r = f2_rint(v);
+    return r < 0 ? 0 : (r > hi ? hi : r);
+}
+
+// Ray of pixel (pi, pj): the definition's FP64 geometry (pixel-centre ray, slab clip against
+// [0, (n - 1) h], N = ceil(L / delta) segments, midpoints) evaluated in double-float FP32, which
+// carries ~47 bits through these steps: N and the 32.32 fixed-point positions come out as the FP64
+// definition's except where a quantity lies within ~1e-13 relative of a rounding or ceiling boundary
+// (positions within one unit of 2^-32 voxel on a million-ray CPU comparison, N identical).
 __device__ __forceinline__ RayGeo ray_setup(const KCam cam, int pi, int pj, const KGrid &g)
 {
 #pragma clang fp contract(off)
     RayGeo r;
     r.N = 0;
-    const double fi = pi + 0.5, fj = pj + 0.5;
-    double o[3], d[3];
+    const float fi = (float)pi + 0.5f, fj = (float)pj + 0.5f;  // exact below 2^23
+    F2 o[3], d[3];
     if (cam.persp) {
-        double n2 = 0.0;
+        F2 n2 = f2(0.f);
         for (int a = 0; a < 3; ++a) {
-            o[a] = cam.o[a];
-            d[a] = (double)cam.d0[a] + fi * (double)cam.du[a] + fj * (double)cam.dv[a];
-            n2 += d[a] * d[a];
+            o[a] = f2(cam.o[a]);
+            d[a] = f2_add(f2_add(f2(cam.d0[a]), two_prod(fi, cam.du[a])), two_prod(fj, cam.dv[a]));
+            n2 = f2_add(n2, f2_mul(d[a], d[a]));
         }
-        const double nn = sqrt(n2);
-        for (int a = 0; a < 3; ++a) d[a] /= nn;
+        if (!(n2.hi > 0.f)) return r;
+        const F2 inn = f2_recip(f2_sqrt(n2));
+        for (int a = 0; a < 3; ++a) d[a] = f2_mul(d[a], inn);
     } else {
         for (int a = 0; a < 3; ++a) {
-            o[a] = (double)cam.o[a] + fi * (double)cam.du[a] + fj * (double)cam.dv[a];
-            d[a] = cam.d0[a];
+            o[a] = f2_add(f2_add(f2(cam.o[a]), two_prod(fi, cam.du[a])), two_prod(fj, cam.dv[a]));
+            d[a] = f2(cam.d0[a]);
         }
     }
-    double t0 = -INFINITY, t1 = INFINITY;
+    bool any = false;
+    F2 t0 = f2(0.f), t1 = f2(0.f);
     for (int a = 0; a < 3; ++a) {
-        const double hi = (double)(g.n[a] - 1) * (double)g.h[a];
-        if (d[a] == 0.0) {
-            if (o[a] < 0.0 || o[a] > hi) return r;
+        const F2 hi = two_prod((float)(g.n[a] - 1), g.h[a]);
+        if (fabsf(d[a].hi) < 1e-30f) {
+            // parallel to the faces of this axis (a component below 1e-30 puts both slab parameters
+            // beyond 1e30 unless the origin lies on a face): outside, or on a face moving out, misses
+            if (f2_lt(o[a], f2(0.f)) || f2_lt(hi, o[a])) return r;
+            const bool on0 = o[a].hi == 0.f && o[a].lo == 0.f, onh = o[a].hi == hi.hi && o[a].lo == hi.lo;
+            if ((on0 && d[a].hi < 0.f) || (onh && d[a].hi > 0.f)) return r;
             continue;
         }
-        double ta = (0.0 - o[a]) / d[a], tb = (hi - o[a]) / d[a];
-        if (ta > tb) { const double t = ta; ta = tb; tb = t; }
-        if (ta > t0) t0 = ta;
-        if (tb < t1) t1 = tb;
+        // the face at 0 is the entry for a positive component, the face at (n - 1) h otherwise
+        const F2 id = f2_recip(d[a]);
+        const F2 lo_t = f2_mul(f2_neg(o[a]), id), hi_t = f2_mul(f2_sub(hi, o[a]), id);
+        const bool pos = d[a].hi > 0.f;
+        const F2 ta = pos ? lo_t : hi_t, tb = pos ? hi_t : lo_t;
+        if (!any || f2_lt(t0, ta)) t0 = ta;
+        if (!any || f2_lt(tb, t1)) t1 = tb;
+        any = true;
     }
-    const double tn = t0 > 0.0 ? t0 : 0.0, tf = t1;
-    if (!(tf > tn)) return r;
-    const double delta = g.delta;
-    const double L = tf - tn;
-    const double Nd = ceil(L / delta);
-    if (!(Nd >= 1.0) || Nd > 2.0e9) return r;
-    const int N = (int)Nd;
-    const double dlast = L - (double)(N - 1) * delta;
-    const double tfirst = tn + 0.0 * delta + 0.5 * (N == 1 ? dlast : delta);
-    const double tlast = tn + (double)(N - 1) * delta + 0.5 * dlast;
+    if (!any) return r;  // a zero direction
+    const F2 tn = f2_lt(f2(0.f), t0) ? t0 : f2(0.f), tf = t1;
+    if (!f2_lt(tn, tf)) return r;  // also NaN
+    if (!(tf.hi < 3.0e38f)) return r;  // an unbounded chord (a direction component of ~1e-38)
+    const F2 delta = {g.delta_hi, g.delta_lo};
+    const F2 L = f2_sub(tf, tn);
+    const F2 Lq = f2_mul(L, F2{g.idelta_hi, g.idelta_lo});
+    if (!(Lq.hi <= 2.0e9f)) return r;
+    // ceil(Lq): the high part's ceiling unless the high part is an integer, then that plus the low part's
+    const float ch = ceilf(Lq.hi);
+    const int64_t Nl = (ch != Lq.hi) ? (int64_t)ch : (int64_t)Lq.hi + (int64_t)ceilf(Lq.lo);
+    if (Nl < 1 || Nl > 2000000000LL) return r;
+    int N = (int)Nl;
+    F2 nd, dlast;
+    for (int pass = 0; pass < 2; ++pass) {
+        const float nh = (float)(N - 1);
+        const F2 nm1 = {nh, (float)((int64_t)(N - 1) - (int64_t)nh)};  // N - 1 exactly
+        nd = f2_mul(nm1, delta);
+        dlast = f2_sub(L, nd);
+        // L / delta within 2^-40 above an integer (the product L (1 / delta) rounded up past an exact
+        // integer, as on axis-aligned rays, or a last segment below 2^-40 L) is that integer, as the
+        // FP64 quotient of an exact integer ratio is
+        if (pass == 0 && N > 1 && dlast.hi <= 0x1p-40f * L.hi) --N;
+        else break;
+    }
+    const F2 tfirst = f2_add(tn, f2_half(N == 1 ? dlast : delta));
+    const F2 tlast = f2_add(f2_add(tn, nd), f2_half(dlast));
     for (int a = 0; a < 3; ++a) {
-        const double h = g.h[a];
-        r.q0[a] = to_fix((o[a] + tfirst * d[a]) / h, g.n[a]);
-        r.ql[a] = to_fix((o[a] + tlast * d[a]) / h, g.n[a]);
-        int64_t st = (int64_t)__double2ll_rn(delta * d[a] / h * kS32);
+        const F2 ih = {g.ih_hi[a], g.ih_lo[a]};
+        r.q0[a] = to_fix(f2_mul(f2_add(o[a], f2_mul(tfirst, d[a])), ih), g.n[a]);
+        r.ql[a] = to_fix(f2_mul(f2_add(o[a], f2_mul(tlast, d[a])), ih), g.n[a]);
+        const F2 sv = f2_mul(f2_mul(delta, d[a]), ih);
+        int64_t st = f2_rint(F2{sv.hi * 4294967296.f, sv.lo * 4294967296.f});
         if (N >= 3) {
             // the full-segment samples lie between q0 and q0 + (N-2) st; keep that end inside
             const int64_t maxq = (int64_t)(g.n[a] - 1) * (int64_t)4294967296LL - 1;
@@ -93,8 +220,8 @@ __device__ __forceinline__ RayGeo ray_setup(const KCam cam, int pi, int pj, cons
     if (N == 1)
         for (int a = 0; a < 3; ++a) r.q0[a] = r.ql[a];
     r.N = N;
-    r.delta = (float)delta;
-    r.dlast = (float)dlast;
+    r.delta = delta.hi;
+    r.dlast = dlast.hi;
     return r;
 }
 
