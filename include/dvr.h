@@ -20,7 +20,8 @@
  *     Nothing synchronizes the device.  Scalars produced on the device (|grad I|_max) stay there.
  *   - Arguments are validated before anything is enqueued: on a non-OK return nothing was
  *     enqueued and dvr_last_error() describes the problem.  No exception crosses the ABI.
- *   - Outputs are overwritten, never accumulated.
+ *   - Outputs are overwritten, except dL_dvol of dvr_features_backward, which is accumulated into
+ *     (so that the gradient through the TF lookup can be added to it first).
  *   - The transfer function lives in device memory (the analogue of the paper's uniform buffers,
  *     Sec. 4): editing it needs no re-launch setup, and the batched plan picks up the change.
  */
