@@ -541,6 +541,9 @@ static void launch_tx_lds(const float *Hb, float *X, const float *B, const AxisT
 // y: the three z-groups: Y0 = G^T X_xx + (D2 G)^T X_yy + (D1 G)^T X_xy (z operator G),
 // Y1 = G^T X_xz + (D1 G)^T X_yz (z operator D1 G), Y2 = G^T X_zz (z operator D2 G)
 constexpr int kTyRun = 8, kTzRun = 4;
+// waves per workgroup of the fixed-radius y and z transposes (y: one z-slice each; z: consecutive
+// stretches of 64 plane positions): one-wave workgroups are limited by the workgroup slots of a CU
+constexpr int kTWaves = 4;
 template <int kTRun>
 __global__ __launch_bounds__(64) void k_ty_run(const float *__restrict__ X, float *__restrict__ Y,
                                                const float *__restrict__ B, int nx, int ny, int nz, int R)
@@ -629,12 +632,13 @@ __global__ __launch_bounds__(64) void k_tz_run(const float *__restrict__ Y, floa
 // band offset d = q - j + 2R, both known at compile time, so only the axis ends and the run's
 // ragged tail are tested at run time.  Same rows, products and order: the same bits.
 template <int K, int R>
-__global__ __launch_bounds__(64) void k_ty_run_r(const float *__restrict__ X, float *__restrict__ Y,
-                                                 const float *__restrict__ B, int nx, int ny, int nz)
+__global__ __launch_bounds__(64 * kTWaves) void k_ty_run_r(const float *__restrict__ X, float *__restrict__ Y,
+                                                           const float *__restrict__ B, int nx, int ny, int nz)
 {
-    const int x = (int)(blockIdx.x * 64u + threadIdx.x);
-    if (x >= nx) return;
-    const int yb = (int)blockIdx.y * K, z = (int)blockIdx.z;
+    const int x = (int)(blockIdx.x * 64u + (threadIdx.x & 63u));
+    const int z = (int)(blockIdx.z * kTWaves + (threadIdx.x >> 6));
+    if (x >= nx || z >= nz) return;
+    const int yb = (int)blockIdx.y * K;
     const int nq = min(K, ny - yb);
     const size_t plane = (size_t)nx * (size_t)ny, N = plane * (size_t)nz;
     const size_t col = (size_t)z * plane + (size_t)x;
@@ -675,11 +679,11 @@ __global__ __launch_bounds__(64) void k_ty_run_r(const float *__restrict__ X, fl
 }
 
 template <int K, int R>
-__global__ __launch_bounds__(64) void k_tz_run_r(const float *__restrict__ Y, float *__restrict__ dvol,
-                                                 const float *__restrict__ B, int nx, int ny, int nz)
+__global__ __launch_bounds__(64 * kTWaves) void k_tz_run_r(const float *__restrict__ Y, float *__restrict__ dvol,
+                                                           const float *__restrict__ B, int nx, int ny, int nz)
 {
     const size_t plane = (size_t)nx * (size_t)ny;
-    const size_t e = (size_t)blockIdx.x * 64u + threadIdx.x;
+    const size_t e = (size_t)blockIdx.x * (64u * kTWaves) + threadIdx.x;
     if (e >= plane) return;
     const int zb = (int)blockIdx.y * K;
     const int nq = min(K, nz - zb);
@@ -713,14 +717,14 @@ __global__ __launch_bounds__(64) void k_tz_run_r(const float *__restrict__ Y, fl
 // the fixed-radius y and z transposes for radii 2..10 (runs of kTyRunR, kTzRunR), else the generic
 // ones (runs of kTyRun, kTzRun)
 constexpr int kTyRunR = 8, kTzRunR = 8;
-static dim3 ty_grid(const dvr_grid &g, int K)
+static dim3 ty_grid(const dvr_grid &g, int K, int nw = 1)
 {
-    return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + K - 1) / K), (unsigned)g.nz);
+    return dim3((unsigned)((g.nx + 63) / 64), (unsigned)((g.ny + K - 1) / K), (unsigned)((g.nz + nw - 1) / nw));
 }
-static dim3 tz_grid(const dvr_grid &g, int K)
+static dim3 tz_grid(const dvr_grid &g, int K, int nw = 1)
 {
     const size_t plane = (size_t)g.nx * (size_t)g.ny;
-    return dim3((unsigned)((plane + 63) / 64), (unsigned)((g.nz + K - 1) / K));
+    return dim3((unsigned)((plane + 64 * nw - 1) / (64 * nw)), (unsigned)((g.nz + K - 1) / K));
 }
 
 template <int R>
@@ -730,7 +734,8 @@ static void launch_ty(const float *X, float *Y, const float *B, int Ry, const dv
         hipLaunchKernelGGL(k_ty_run<kTyRun>, ty_grid(g, kTyRun), dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz, Ry);
     } else {
         if (Ry != R) return launch_ty<R + 1>(X, Y, B, Ry, g, st);
-        hipLaunchKernelGGL((k_ty_run_r<kTyRunR, R>), ty_grid(g, kTyRunR), dim3(64), 0, st, X, Y, B, g.nx, g.ny, g.nz);
+        hipLaunchKernelGGL((k_ty_run_r<kTyRunR, R>), ty_grid(g, kTyRunR, kTWaves), dim3(64 * kTWaves), 0, st, X, Y, B,
+                           g.nx, g.ny, g.nz);
     }
 }
 
@@ -741,8 +746,8 @@ static void launch_tz(const float *Y, float *dvol, const float *B, int Rz, const
         hipLaunchKernelGGL(k_tz_run<kTzRun>, tz_grid(g, kTzRun), dim3(64), 0, st, Y, dvol, B, g.nx, g.ny, g.nz, Rz);
     } else {
         if (Rz != R) return launch_tz<R + 1>(Y, dvol, B, Rz, g, st);
-        hipLaunchKernelGGL((k_tz_run_r<kTzRunR, R>), tz_grid(g, kTzRunR), dim3(64), 0, st, Y, dvol, B, g.nx, g.ny,
-                           g.nz);
+        hipLaunchKernelGGL((k_tz_run_r<kTzRunR, R>), tz_grid(g, kTzRunR, kTWaves), dim3(64 * kTWaves), 0, st, Y, dvol,
+                           B, g.nx, g.ny, g.nz);
     }
 }
 
