@@ -122,6 +122,7 @@ def _rp(**kw):
     (4, _rp(), [_cam(4, 4), _cam(4, 5)], -1),
     (4, _rp(), [_cam(persp=2)], -1),
     (4, _rp(), [_cam(0, 4)], -1),
+    (4, _rp(), [_cam((1 << 23) + 1, 1)], -1),   # pixel centres beyond exact FP32
 ])
 def test_render_rejects_bad_params(L, tf_K, rp, cams, code):
     arr = (abi.Camera * len(cams))(*cams)
