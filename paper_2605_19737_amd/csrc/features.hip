@@ -99,16 +99,20 @@ __global__ __launch_bounds__(NT) void k_xypass(XYArgs a, ScaleTaps taps)
 // slice is computed.
 constexpr int kZRun = 1;
 
+// One slice per workgroup, the y-filtered fields written over the staged ones (one LDS area of
+// max(NF, NFY) floats): 25 instead of 41 KB at radius 10, six workgroups a CU instead of three.  At
+// radii 6-9 the compiler otherwise takes 103-128 VGPRs (four waves per SIMD) for the y filters'
+// registers; held to six waves it needs 57-64, without spills (radius 7: 0.142 -> 0.127 ms on the head).
 template <int DT, int OUT_DT, int LAYOUT, int R>
-__global__ __launch_bounds__(NT) void k_xypass_r(XYArgs a, ScaleTaps taps)
+__global__ __launch_bounds__(NT, (R >= 6 && R <= 9) ? 6 : 1) void k_xypass_r(XYArgs a, ScaleTaps taps)
 {
     using T = XYTileR<R, TX, TY>;
-    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY>;
-    __shared__ float F[T::NF];
-    __shared__ float Fy[T::NFY];
+    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY, ScaleTaps, kZRun == 1>;
+    __shared__ float F[kZRun == 1 ? (T::NF > T::NFY ? T::NF : T::NFY) : T::NF];
+    __shared__ float Fy[kZRun == 1 ? 1 : T::NFY];
     float vmax;
     if constexpr (kZRun == 1) {
-        S s(a, taps, F, Fy, blockIdx.x * TX, blockIdx.y * TY);
+        S s(a, taps, F, F, blockIdx.x * TX, blockIdx.y * TY);
         const int z = blockIdx.z;
         s.load(z);
         s.store();

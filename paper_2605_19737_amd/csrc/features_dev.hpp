@@ -750,7 +750,11 @@ struct XYTileR {
 // One 64 x TY tile of the fixed-radius pass, for a run of z slices: the loads of a slice (its staged
 // z-filtered fields with halo, the intensities of the gradient and, after the first scale, the V so
 // far) are issued into registers while the previous slice is computed.
-template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST = ScaleTaps>
+// ALIAS: the y-filtered fields are written over the staged ones (F == Fy, max(NF, NFY) floats of
+// LDS instead of NF + NFY): the y filters keep their results in registers until every lane has
+// finished reading the staged rows, and a barrier separates the x filters from the epilogue's
+// compaction lists, which reuse the same area.  Less LDS per workgroup, more workgroups per CU.
+template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST = ScaleTaps, bool ALIAS = false>
 struct XYSlab {
     using T = XYTileR<R, TX, TY>;
     static constexpr int W = T::W, HH = T::HH;
@@ -876,6 +880,77 @@ struct XYSlab {
         const auto &tx = taps.ax[0];
         const auto &ty = taps.ax[1];
         const int t = threadIdx.x;
+        if constexpr (ALIAS) {
+            y_filters_aliased(ty, t);
+        } else {
+            y_filters(ty, t);
+        }
+        return x_filters_and_out(z, tx, Ic, Vc);
+    }
+
+    // y filters into registers, then over the staged rows (ALIAS)
+    template <typename AT>
+    __device__ __forceinline__ void y_filters_aliased(const AT &ty, int t)
+    {
+        constexpr int kIt = (TY * W + NT - 1) / NT;
+        float ry[kIt][6];
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int p = t + it * NT;
+            if (p < TY * W) {
+                const int yy = p / W, xx = p - yy * W;
+                const lds_f *b = (const lds_f *)(F) + (yy * W + xx);
+                asm volatile("" : "+v"(b));
+                auto f0 = [&](int m) { return b[(0 * HH + R + m) * W]; };
+                auto f1 = [&](int m) { return b[(1 * HH + R + m) * W]; };
+                auto f2 = [&](int m) { return b[(2 * HH + R + m) * W]; };
+                const Line3 r0 = r3<R>(ty, 0, f0);
+                ry[it][0] = r0.g;
+                ry[it][1] = r0.d1;
+                ry[it][2] = r0.d2;
+                ry[it][3] = rG<R>(ty, f1);
+                ry[it][4] = rD1<R>(ty, 0, f1);
+                ry[it][5] = rG<R>(ty, f2);
+            }
+        }
+        if (y0 == 0 || y0 + TY >= ny) {
+#pragma unroll
+            for (int it = 0; it < kIt; ++it) {
+                const int p = t + it * NT;
+                if (p < TY * W) {
+                    const int yy = p / W, xx = p - yy * W;
+                    const int gy = y0 + yy;
+                    auto f0 = [&](int m) { return F[(0 * HH + yy + R + m) * W + xx]; };
+                    auto f1 = [&](int m) { return F[(1 * HH + yy + R + m) * W + xx]; };
+                    if (gy == 0) {
+                        ry[it][1] = rD1<R>(ty, 1, f0);
+                        ry[it][2] = rD2<R>(ty, 1, f0);
+                        ry[it][4] = rD1<R>(ty, 1, f1);
+                    }
+                    if (gy == ny - 1) {
+                        ry[it][1] = rD1<R>(ty, 2, f0);
+                        ry[it][2] = rD2<R>(ty, 2, f0);
+                        ry[it][4] = rD1<R>(ty, 2, f1);
+                    }
+                }
+            }
+        }
+        __syncthreads();  // every lane's reads of the staged rows are done
+#pragma unroll
+        for (int it = 0; it < kIt; ++it) {
+            const int p = t + it * NT;
+            if (p < TY * W) {
+#pragma unroll
+                for (int k = 0; k < 6; ++k) Fy[k * TY * W + p] = ry[it][k];
+            }
+        }
+        __syncthreads();
+    }
+
+    // y filters from F into Fy (separate areas)
+    template <typename AT>
+    __device__ __forceinline__ void y_filters(const AT &ty, int t)
+    {
         // y filters: all TY rows x W columns of the tile; interior sums everywhere, then the one-sided
         // forms on the first and last row of the volume
         for (int p = t; p < TY * W; p += NT) {
@@ -921,7 +996,12 @@ struct XYSlab {
             }
         }
         __syncthreads();
+    }
 
+    template <typename AT>
+    __device__ __forceinline__ float x_filters_and_out(int z, const AT &tx, const float (&Ic)[NV][7],
+                                                       const float (&Vc)[NV])
+    {
         // x filters of this lane's voxels (rows wv + NW i, column lane), the same way
         float H[NV][6];
         uint32_t v[NV];
@@ -966,7 +1046,9 @@ struct XYSlab {
                 }
             }
         }
-        // the staged fields are dead after the y filters: the compaction lists reuse them
+        // the staged fields are dead after the y filters: the compaction lists reuse them (in the
+        // aliased form they hold the y-filtered fields, which every lane must have read first)
+        if constexpr (ALIAS) __syncthreads();
         float vmax = 0.f;
         voxels_out<OUT_DT, LAYOUT, NV>(a, taps.sigma2, H, Ic, v, live, N, vmax, F, &Vc);
         return vmax;
