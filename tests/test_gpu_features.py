@@ -59,6 +59,17 @@ def test_features_frangi_auto_c():
     _compare(w.vol[:40, :50, :60], w.spacing, [1.0, 1.5], -1.0, label="auto-c")
 
 
+@pytest.mark.parametrize("layout", [abi.DVR_PLANAR, abi.DVR_SPLIT])
+def test_features_every_fixed_radius(layout):
+    """Each stencil radius of the fixed-radius kernels (2..10, sigma = r/3 mm at 1 mm spacing for
+    r = 1..9, one scale per call so that kappa checks that radius's Hessian everywhere) on a crop
+    of the head with vessels that spans several 64 x 8 tiles with ragged tails."""
+    w = phantoms.c2(8, 8, views=[0])
+    vol = w.vol[60:97, 70:140, 40:130]
+    for r in range(1, 10):
+        _compare(vol, (1.0, 1.0, 1.0), [r / 3.0], w.c, layout=layout, label=f"radius {r + 1}")
+
+
 def test_features_head_three_scales():
     """The 181x217x181 head phantom with vessels at sigma = {1, 2, 3} (the benchmarked workload)."""
     w = phantoms.c2(8, 8, views=[0])
