@@ -179,7 +179,7 @@ __device__ __forceinline__ bool xy_fixed(const XYArgs &a, const ST &taps, int Rr
         return false;
     } else {
         if (Rr != R) return xy_fixed<DT, LAYOUT, TX, TY, R + 1>(a, taps, Rr, x0, y0, z0, z1, lds, vmax);
-        vmax = xy_run_r<DT, DT, LAYOUT, R, TX, TY>(a, taps, x0, y0, z0, z1, lds, lds + XYTileR<R, TX, TY>::NF);
+        vmax = xy_run_r<DT, DT, LAYOUT, R, TX, TY>(a, taps, x0, y0, z0, z1, lds, lds);
         return true;
     }
 }

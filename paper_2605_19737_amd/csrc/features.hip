@@ -107,9 +107,8 @@ template <int DT, int OUT_DT, int LAYOUT, int R>
 __global__ __launch_bounds__(NT, (R >= 6 && R <= 9) ? 6 : 1) void k_xypass_r(XYArgs a, ScaleTaps taps)
 {
     using T = XYTileR<R, TX, TY>;
-    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY, ScaleTaps, kZRun == 1>;
-    __shared__ float F[kZRun == 1 ? (T::NF > T::NFY ? T::NF : T::NFY) : T::NF];
-    __shared__ float Fy[kZRun == 1 ? 1 : T::NFY];
+    using S = XYSlab<DT, OUT_DT, LAYOUT, R, TX, TY>;
+    __shared__ float F[T::NF > T::NFY ? T::NF : T::NFY];
     float vmax;
     if constexpr (kZRun == 1) {
         S s(a, taps, F, F, blockIdx.x * TX, blockIdx.y * TY);
@@ -120,7 +119,7 @@ __global__ __launch_bounds__(NT, (R >= 6 && R <= 9) ? 6 : 1) void k_xypass_r(XYA
         vmax = s.compute(z, s.In, s.Vp);
     } else {
         const int z0 = blockIdx.z * kZRun, z1 = min(z0 + kZRun, a.nz);
-        vmax = xy_run_r<DT, OUT_DT, LAYOUT, R, TX, TY>(a, taps, blockIdx.x * TX, blockIdx.y * TY, z0, z1, F, Fy);
+        vmax = xy_run_r<DT, OUT_DT, LAYOUT, R, TX, TY>(a, taps, blockIdx.x * TX, blockIdx.y * TY, z0, z1, F, F);
     }
     if (a.fro_pass || a.first) {
         vmax = wave_max(vmax);

@@ -750,11 +750,11 @@ struct XYTileR {
 // One 64 x TY tile of the fixed-radius pass, for a run of z slices: the loads of a slice (its staged
 // z-filtered fields with halo, the intensities of the gradient and, after the first scale, the V so
 // far) are issued into registers while the previous slice is computed.
-// ALIAS: the y-filtered fields are written over the staged ones (F == Fy, max(NF, NFY) floats of
-// LDS instead of NF + NFY): the y filters keep their results in registers until every lane has
-// finished reading the staged rows, and a barrier separates the x filters from the epilogue's
-// compaction lists, which reuse the same area.  Less LDS per workgroup, more workgroups per CU.
-template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST = ScaleTaps, bool ALIAS = false>
+// The y-filtered fields may be written over the staged ones (F == Fy: max(NF, NFY) floats of LDS
+// instead of NF + NFY): the y filters keep their results in registers until every lane has finished
+// reading the staged rows, and a barrier separates the x filters from the epilogue's compaction
+// lists, which reuse the staging area.  Less LDS per workgroup, more workgroups per CU.
+template <int DT, int OUT_DT, int LAYOUT, int R, int TX, int TY, typename ST = ScaleTaps>
 struct XYSlab {
     using T = XYTileR<R, TX, TY>;
     static constexpr int W = T::W, HH = T::HH;
@@ -880,17 +880,15 @@ struct XYSlab {
         const auto &tx = taps.ax[0];
         const auto &ty = taps.ax[1];
         const int t = threadIdx.x;
-        if constexpr (ALIAS) {
-            y_filters_aliased(ty, t);
-        } else {
-            y_filters(ty, t);
-        }
+        y_filters(ty, t);
         return x_filters_and_out(z, tx, Ic, Vc);
     }
 
-    // y filters into registers, then over the staged rows (ALIAS)
+    // y filters: all TY rows x W columns of the tile into registers (interior sums everywhere, then
+    // the one-sided forms on the first and last row of the volume), then into Fy once every lane has
+    // read the staged rows
     template <typename AT>
-    __device__ __forceinline__ void y_filters_aliased(const AT &ty, int t)
+    __device__ __forceinline__ void y_filters(const AT &ty, int t)
     {
         constexpr int kIt = (TY * W + NT - 1) / NT;
         float ry[kIt][6];
@@ -947,57 +945,6 @@ struct XYSlab {
         __syncthreads();
     }
 
-    // y filters from F into Fy (separate areas)
-    template <typename AT>
-    __device__ __forceinline__ void y_filters(const AT &ty, int t)
-    {
-        // y filters: all TY rows x W columns of the tile; interior sums everywhere, then the one-sided
-        // forms on the first and last row of the volume
-        for (int p = t; p < TY * W; p += NT) {
-            const int yy = p / W, xx = p - yy * W;
-            // one opaque LDS base per position: every tap's offset is then an immediate of its LDS read
-            const lds_f *b = (const lds_f *)(F) + (yy * W + xx);
-            asm volatile("" : "+v"(b));
-            auto f0 = [&](int m) { return b[(0 * HH + R + m) * W]; };
-            auto f1 = [&](int m) { return b[(1 * HH + R + m) * W]; };
-            auto f2 = [&](int m) { return b[(2 * HH + R + m) * W]; };
-            const Line3 r0 = r3<R>(ty, 0, f0);   // Gy Gz, D1y Gz, D2y Gz
-            const float r1g = rG<R>(ty, f1);      // Gy D1z
-            const float r1d = rD1<R>(ty, 0, f1);  // D1y D1z
-            const float r2 = rG<R>(ty, f2);       // Gy D2z
-            Fy[0 * TY * W + p] = r0.g;
-            Fy[1 * TY * W + p] = r0.d1;
-            Fy[2 * TY * W + p] = r0.d2;
-            Fy[3 * TY * W + p] = r1g;
-            Fy[4 * TY * W + p] = r1d;
-            Fy[5 * TY * W + p] = r2;
-        }
-        // the first and last row of the volume take the one-sided differences: only tiles that hold one
-        // (a workgroup-uniform test) redo their difference fields there, each position by the lane that
-        // computed it above
-        if (y0 == 0 || y0 + TY >= ny) {
-            for (int p = t; p < TY * W; p += NT) {
-                const int yy = p / W, xx = p - yy * W;
-                const int gy = y0 + yy;
-                auto f0 = [&](int m) { return F[(0 * HH + yy + R + m) * W + xx]; };
-                auto f1 = [&](int m) { return F[(1 * HH + yy + R + m) * W + xx]; };
-                // two branches with the class a constant (a class chosen at run time would make the
-                // compiler copy both tap sets to vector registers on every path)
-                if (gy == 0) {
-                    Fy[1 * TY * W + p] = rD1<R>(ty, 1, f0);
-                    Fy[2 * TY * W + p] = rD2<R>(ty, 1, f0);
-                    Fy[4 * TY * W + p] = rD1<R>(ty, 1, f1);
-                }
-                if (gy == ny - 1) {
-                    Fy[1 * TY * W + p] = rD1<R>(ty, 2, f0);
-                    Fy[2 * TY * W + p] = rD2<R>(ty, 2, f0);
-                    Fy[4 * TY * W + p] = rD1<R>(ty, 2, f1);
-                }
-            }
-        }
-        __syncthreads();
-    }
-
     template <typename AT>
     __device__ __forceinline__ float x_filters_and_out(int z, const AT &tx, const float (&Ic)[NV][7],
                                                        const float (&Vc)[NV])
@@ -1046,9 +993,9 @@ struct XYSlab {
                 }
             }
         }
-        // the staged fields are dead after the y filters: the compaction lists reuse them (in the
-        // aliased form they hold the y-filtered fields, which every lane must have read first)
-        if constexpr (ALIAS) __syncthreads();
+        // the staged fields are dead after the y filters: the compaction lists reuse them (when the
+        // y-filtered fields were written over them, every lane must have read those first)
+        __syncthreads();
         float vmax = 0.f;
         voxels_out<OUT_DT, LAYOUT, NV>(a, taps.sigma2, H, Ic, v, live, N, vmax, F, &Vc);
         return vmax;
